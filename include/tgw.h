@@ -1,0 +1,237 @@
+/*
+ * tgw.h -- C ABI of the MI355X (gfx950) phenotype-panel linear association scan.
+ *
+ * The library computes, for every marker m and phenotype p of one or more
+ * phenotype panels, the ordinary least-squares statistics of the marker
+ * coefficient in  y_p ~ 1 + C + g_m  (r, beta, SE, t and -log10 p), with
+ * missing genotype calls replaced by the marker's mean over observed calls.
+ * It follows the paper's Methods 2.2 (Association kernel):
+ *   - the phenotype panel is mean-centred, projected off an orthonormal basis
+ *     Q of the covariate space and scaled to unit columns ONCE (Eq. 1 and the
+ *     standardization after it)                  -> tgw_prepare_phenotypes
+ *   - genotypes are then streamed in marker blocks, each block contracted
+ *     with the prepared panel (Eq. 2) and turned into t-statistics (Eq. 3)
+ *     and p-values                                -> tgw_scan
+ *   - Q comes from a Householder QR of [1 | C]    -> tgw_fit_covariates
+ * Readings of points the paper leaves open (used throughout):
+ *   - genotypes are covariate-adjusted as well (exact Frisch-Waugh-Lovell
+ *     partial correlation); at K = 0 this is exactly the paper's Eq. 2-3;
+ *   - df = N - q - 1 with q = K + 1 columns in Q (the paper's N - 2 at K = 0);
+ *   - p-values are two-sided Student t with df degrees of freedom;
+ *   - missing calls are imputed with the marker mean over observed calls.
+ *
+ * Conventions
+ *   - "device" pointers point to memory on the current HIP device; the caller
+ *     owns every buffer it passes in (covariates, phenotypes, genotypes,
+ *     outputs).  Handles own their device memory (allocated with hipMalloc at
+ *     creation) and free it in tgw_*_free.
+ *   - "stream" is a hipStream_t passed as void*; NULL means the default stream.
+ *   - All functions return a tgw_status; TGW_OK is 0.  On error nothing is
+ *     enqueued and tgw_last_error() gives a thread-local message.  C++
+ *     exceptions never cross this boundary.
+ *   - Handles are immutable after creation except tgw_plan (see tgw_scan).
+ */
+#ifndef TGW_H
+#define TGW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TGW_ABI_VERSION 1
+
+typedef enum {
+  TGW_OK = 0,
+  TGW_ERR_INVALID_ARG = 1,    /* null pointer, negative size, bad enum */
+  TGW_ERR_SHAPE = 2,          /* inconsistent sizes / strides / alignment */
+  TGW_ERR_RANK_DEFICIENT = 3, /* [1 | C] rank deficient: |R_jj| <= 1e-10 max|R_ii| */
+  TGW_ERR_NONFINITE = 4,      /* NaN or Inf in covariates or phenotypes */
+  TGW_ERR_DEVICE = 5,         /* HIP runtime error (incl. earlier async faults) */
+  TGW_ERR_OUT_OF_MEMORY = 6,
+  TGW_ERR_UNSUPPORTED = 7,    /* e.g. more than 31 covariates, wrong GPU */
+  TGW_ERR_TAIL_OVERFLOW = 8   /* more extreme-tail tests than the plan's list holds */
+} tgw_status;
+
+/* Arithmetic of the genotype x phenotype contraction (Eq. 2).
+ *  TGW_PREC_FP32  : FP32 operands on the FP32 matrix cores, FP32 accumulate.
+ *  TGW_PREC_SPLIT : the prepared panel is split into BF16 hi + lo terms; the
+ *                   genotype operand is exact in BF16 (re-centred calls, see
+ *                   tgw_scan); two BF16 matrix-core passes, FP32 accumulate.
+ * Covariate QR, phenotype norms and the extreme-tail p-values stay FP64. */
+typedef enum { TGW_PREC_FP32 = 0, TGW_PREC_SPLIT = 1 } tgw_precision;
+
+/* Meaning of the 2-bit genotype codes (sample i of a row sits at bits
+ * 2*(i & 3) of byte i >> 2, as in PLINK .bed rows).
+ *  TGW_CODE_DOSAGE    : 0, 1, 2 = copies of the counted allele, 3 = missing.
+ *  TGW_CODE_PLINK_BED : 0 -> 0, 1 -> missing, 2 -> 1, 3 -> 2 (copies of the
+ *                       second allele). */
+typedef enum { TGW_CODE_DOSAGE = 0, TGW_CODE_PLINK_BED = 1 } tgw_geno_code;
+
+typedef struct tgw_covariates tgw_covariates; /* Q of one covariate matrix   */
+typedef struct tgw_panel tgw_panel;           /* one prepared phenotype panel */
+typedef struct tgw_plan tgw_plan;             /* panels + scan workspace      */
+typedef struct tgw_graph tgw_graph;           /* a captured tgw_scan call     */
+
+/* Output buffers of one panel for one tgw_scan call.  Each array is
+ * (m_end - m_begin) rows x n_pheno columns, row-major with row stride `ld`
+ * elements (ld >= n_pheno): element (m - m_begin, p) holds the statistic of
+ * marker m and phenotype p.  Any pointer may be NULL (not computed/written).
+ *   r        partial correlation of g_m and y_p given [1 | C], in [-1, 1]
+ *   beta     OLS coefficient of g_m (phenotype units per allele)
+ *   se       its standard error
+ *   t        beta / se = r sqrt(df / (1 - r^2))
+ *   nlog10p  -log10 of the two-sided Student-t p-value (df degrees)
+ * Degenerate markers (no observed call, monomorphic among observed calls, or
+ * ||g_res||^2 <= 1e-4 ||g_c||^2, i.e. the covariates explain 99.99 % of the
+ * marker's variance) and degenerate phenotypes (residual norm <= 1e-12 of the
+ * centred norm) give NaN in every output. */
+typedef struct {
+  float* r;
+  float* beta;
+  float* se;
+  float* t;
+  float* nlog10p;
+  int64_t ld;
+} tgw_outputs;
+
+/* Scan plan options; zero-initialise and set what you need. */
+typedef struct {
+  int64_t block_markers; /* markers per internal block (0 = automatic)          */
+  int64_t tail_capacity; /* extreme-tail list entries (0 = 1<<20)                */
+  int32_t tile;          /* tile shape index, < 0 = default (see tgw_plan_info)  */
+  int32_t reserved;
+} tgw_plan_options;
+
+/* ---- library ---------------------------------------------------------- */
+const char* tgw_status_string(tgw_status s);
+const char* tgw_last_error(void);      /* thread-local detail of the last error */
+int32_t tgw_abi_version(void);
+/* Checks that the current device is gfx950 and caches its properties. */
+tgw_status tgw_init(void);
+
+/* ---- covariates (paper Methods 2.2, Eq. 1: Q spans the covariate space) --
+ * Builds Q (n_samples x q, q = n_cov + 1, orthonormal columns) by an FP64
+ * Householder QR of X0 = [1 | C] on the GPU.  The intercept is always added.
+ *   d_C   device FP64, column-major n_samples x n_cov, leading dim ldc >= n_samples
+ *         (may be NULL when n_cov == 0).  Not retained.
+ * Synchronizes `stream` once to report:
+ *   TGW_ERR_NONFINITE if C holds NaN/Inf; TGW_ERR_RANK_DEFICIENT if
+ *   |R_jj| <= 1e-10 max_i |R_ii|; TGW_ERR_SHAPE unless n_samples >= n_cov + 3
+ *   and 0 <= n_cov <= 31. */
+tgw_status tgw_fit_covariates(int64_t n_samples, int32_t n_cov, const double* d_C, int64_t ldc,
+                              void* stream, tgw_covariates** out);
+void tgw_covariates_free(tgw_covariates* cov);
+/* Copies Q (FP64, column-major n x q, leading dim ldq >= n) to device memory. */
+tgw_status tgw_covariates_q(const tgw_covariates* cov, double* d_Q, int64_t ldq, void* stream);
+
+/* ---- phenotype panel (paper Methods 2.2, Eq. 1 + standardization) -------
+ * Once per panel: Y_c = Y - mean(Y); Y_res = (I - Q Q^T) Y_c;
+ * s_p = ||Y_res,p|| (FP64); Y~ = Y_res / s_p; then Y~ is stored in the
+ * scan's operand layout (FP32, or BF16 hi + lo for TGW_PREC_SPLIT) together
+ * with per-column FP64-derived constants and the p-value table for
+ * df = n_samples - q - 1.
+ *   d_Y   device, column-major n_samples x n_pheno, FP32 (y_is_fp64 = 0) or
+ *         FP64 (y_is_fp64 = 1), leading dim ldy >= n_samples.  Not retained.
+ * The panel keeps a reference to `cov`; free panels before their covariates.
+ * Synchronizes `stream` once; TGW_ERR_NONFINITE on NaN/Inf in Y. */
+tgw_status tgw_prepare_phenotypes(const tgw_covariates* cov, int64_t n_pheno, const void* d_Y,
+                                  int32_t y_is_fp64, int64_t ldy, tgw_precision prec,
+                                  void* stream, tgw_panel** out);
+void tgw_panel_free(tgw_panel* panel);
+/* n = samples, p = phenotypes, q = columns of Q, df = residual degrees of freedom. */
+tgw_status tgw_panel_info(const tgw_panel* panel, int64_t* n, int64_t* p, int32_t* q, int64_t* df);
+
+/* ---- scan plan ------------------------------------------------------------
+ * Groups one or more prepared panels that share n_samples and precision
+ * (the batching form: uneven P and K run through one persistent launch over
+ * the virtual concatenation of all their columns) and allocates the scan
+ * workspace.  `panels` must stay alive while the plan is used. */
+tgw_status tgw_plan_create(const tgw_panel* const* panels, int32_t n_panels,
+                           const tgw_plan_options* opts, tgw_plan** out);
+void tgw_plan_free(tgw_plan* plan);
+/* tile = chosen tile shape index; n_tiles = number of shapes;
+ * block_markers = markers per internal block. */
+tgw_status tgw_plan_info(const tgw_plan* plan, int32_t* tile, int32_t* n_tiles, int64_t* block_markers);
+/* Tile shape idx as (markers per workgroup tile, columns per tile, waves). */
+tgw_status tgw_tile_shape(int32_t idx, int32_t* tile_markers, int32_t* tile_cols, int32_t* waves);
+/* Autotuner: times every tile shape on markers [m_begin, m_end) of d_geno
+ * (one block at most) with HIP events, keeps the fastest for this plan and
+ * records it in a JSON cache keyed by (arch, padded samples, column blocks,
+ * panels, precision): $TGW_TUNE_CACHE, default ~/.cache/tgw/tune.json.  A
+ * later plan with the same key takes the cached shape without timing.
+ * Writes scratch results into `outs`; synchronizes `stream`.  best_ms may be
+ * NULL. */
+tgw_status tgw_plan_autotune(tgw_plan* plan, const uint8_t* d_geno, int64_t n_markers, int64_t row_bytes,
+                             tgw_geno_code code, int64_t m_begin, int64_t m_end, const tgw_outputs* outs,
+                             void* stream, double* best_ms);
+
+/* ---- the scan (paper Methods 2.2, Eq. 2-3 and the p-value conversion) ----
+ * Streams markers [m_begin, m_end) of the packed genotype matrix through
+ * every panel of the plan and writes each panel's outputs.
+ *   d_geno     device, n_markers rows of row_bytes bytes (2-bit codes, see
+ *              tgw_geno_code); 16-byte aligned, row_bytes a multiple of 16 and
+ *              >= 16 * ceil(n_samples / 64).  Bytes past sample n_samples-1
+ *              are ignored.
+ *   outs       n_panels entries, in the plan's panel order (see tgw_outputs).
+ * Per marker: exact integer counts give the mean mu; each call g is fed to
+ * the matrix cores as g - c with c = round(64 mu)/64 (exact in BF16 and FP32),
+ * a missing call as mu - c rounded to the operand type (error <= 2^-16 in
+ * BF16); the intercept of the covariate projection removes c exactly.
+ * Asynchronous: enqueues kernels on `stream`, allocates nothing and does not
+ * synchronize; capturable in a HIP graph.  The plan's workspace is reused, so
+ * calls with the same plan must not run concurrently on different streams.
+ * Extreme tails (|t| > 40) are finished in FP64 by a follow-up kernel; if
+ * more than tail_capacity such tests occur in one call, the excess keep a
+ * lower bound and tgw_plan_check reports TGW_ERR_TAIL_OVERFLOW. */
+tgw_status tgw_scan(tgw_plan* plan, const uint8_t* d_geno, int64_t n_markers, int64_t row_bytes,
+                    tgw_geno_code code, int64_t m_begin, int64_t m_end, const tgw_outputs* outs,
+                    void* stream);
+/* Synchronizes `stream` and reports device errors / tail overflow of the
+ * last tgw_scan on this plan; n_tail receives the number of tail tests. */
+tgw_status tgw_plan_check(tgw_plan* plan, void* stream, int64_t* n_tail);
+
+/* ---- kernel timing ----------------------------------------------------------
+ * With profiling on, every tgw_scan on this plan records HIP events on its
+ * stream around each launch of the main contraction kernel (the dominant
+ * kernel).  tgw_plan_profile_read synchronizes `stream`, returns the summed
+ * kernel time in ms and the number of launches since the last read, and
+ * clears the record.  Not for use inside graph capture. */
+tgw_status tgw_plan_profile(tgw_plan* plan, int32_t enable);
+tgw_status tgw_plan_profile_read(tgw_plan* plan, void* stream, double* main_ms, int64_t* launches);
+
+/* ---- graph capture ---------------------------------------------------------
+ * Captures one tgw_scan call (same arguments) into an instantiated HIP graph;
+ * tgw_graph_launch replays it on `stream`.  The graph refers to the plan's
+ * workspace and to the given buffers, which must outlive it. */
+tgw_status tgw_graph_create(tgw_plan* plan, const uint8_t* d_geno, int64_t n_markers, int64_t row_bytes,
+                            tgw_geno_code code, int64_t m_begin, int64_t m_end,
+                            const tgw_outputs* outs, tgw_graph** out);
+tgw_status tgw_graph_launch(tgw_graph* graph, void* stream);
+void tgw_graph_free(tgw_graph* graph);
+
+/* ---- test hook (exactness of the contraction) -------------------------------
+ * Writes the raw FP32 contraction S[m][c] = sum_i a_m(i) * v_c(i) of markers
+ * [m_begin, m_end) with the panel's stored operand columns v_c (the prepared
+ * Y~ in its operand precision, hi + lo for TGW_PREC_SPLIT), where a_m(i) is the
+ * re-centred genotype operand described at tgw_scan.  d_S is row-major with
+ * leading dim lds >= n_pheno.  Used by tests with integer-valued operands. */
+tgw_status tgw_debug_contract(tgw_plan* plan, const uint8_t* d_geno, int64_t n_markers, int64_t row_bytes,
+                              tgw_geno_code code, int64_t m_begin, int64_t m_end, float* d_S, int64_t lds,
+                              void* stream);
+/* Overwrites a panel's stored operand columns with raw values (no centring,
+ * residualization or scaling): d_V device FP32 column-major n x p (ld ldv).
+ * For TGW_PREC_SPLIT, hi = bf16(v) and lo = bf16(v - hi).  Test use only. */
+tgw_status tgw_debug_set_operand(tgw_panel* panel, const float* d_V, int64_t ldv, void* stream);
+/* Per-marker re-centring constant c = round(64 mu)/64 and mean mu of markers
+ * [m_begin, m_end) (device FP64 arrays, may be NULL).  Test use only. */
+tgw_status tgw_debug_marker_stats(tgw_plan* plan, const uint8_t* d_geno, int64_t n_markers, int64_t row_bytes,
+                                  tgw_geno_code code, int64_t m_begin, int64_t m_end, double* d_shift,
+                                  double* d_mean, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TGW_H */

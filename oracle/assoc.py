@@ -165,7 +165,7 @@ def scan(G: np.ndarray, C: np.ndarray, Y: np.ndarray, Q: np.ndarray = None):
         a[bad] = np.nan
     nl = nlog10p_two_sided(t, df)
     return dict(r=r, beta=beta, se=se, t=t, nlog10p=nl, df=df, q=q,
-                mu=mu, n_obs=n_obs, h=h, scale=s, marker_valid=mvalid, pheno_valid=yvalid)
+                mu=mu, n_obs=n_obs, h=h, gc2=gc2, scale=s, marker_valid=mvalid, pheno_valid=yvalid)
 
 
 def scan_packed(packed: np.ndarray, n_samples: int, C: np.ndarray, Y: np.ndarray,

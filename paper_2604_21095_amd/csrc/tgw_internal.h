@@ -1,0 +1,161 @@
+// Internal declarations shared by the gfx950 kernels and the host runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tgw {
+
+// ---- operand layout -------------------------------------------------------
+// Samples are processed in chunks of 64 (the contraction's K chunk).  A
+// prepared panel (and the covariate columns used for Q^T g) is stored as
+// column blocks of 32 columns; block (cb, ch) = 8 KiB holding columns
+// 32cb..32cb+31 for samples 64ch..64ch+63, arranged exactly as the matrix
+// core reads them (see kernels: operand_index_split / operand_index_fp32).
+constexpr int kChunk = 64;
+constexpr int kColBlock = 32;
+constexpr int kBlockBytes = 8192;
+constexpr int kSlots = 32;      // correction slots per (marker, panel): dmu, Q^T g
+constexpr int kMaxCov = 31;     // K <= 31 so that q = K + 1 <= 32 slots
+constexpr int kMaxPanelsPerBind = 32;
+// A marker is degenerate when ||g_res||^2 <= kMarkerTol ||g_c||^2.  ||g_res||^2
+// is ||g_c||^2 - sum_k (q_k^T g)^2 with q_k^T g from the FP32-accumulated
+// contraction, which resolves the difference to about 1e-6 ||g_c||^2.
+constexpr double kMarkerTol = 1e-4;
+
+// ---- p-value table ----------------------------------------------------------
+constexpr float kTMax = 40.0f;        // |t| beyond this goes to the FP64 tail
+constexpr int kTabPerUnit = 32;       // nodes per unit of |t|
+constexpr int kTabNodes = 40 * 32 + 2;
+
+enum Prec { kFP32 = 0, kSplit = 1 };
+enum Mode { kRaw = 0, kTest = 1 };
+
+// per-marker statistics of one marker block
+struct MarkerStat {
+  double gc2;    // ||g_c||^2 of the mean-imputed marker (exact from integer counts)
+  float dmu;     // mu - c, c = round(64 mu) / 64 (the re-centring constant)
+  int32_t flags; // 1 = degenerate (no observed call or monomorphic)
+  double mu;
+  double shift;  // c
+};
+
+struct PanelDev {
+  const float* scale;   // s_p = ||Y_res,p||
+  const float* invny;   // 1 / ||(I - QQ^T) y_op,p||  (NaN for degenerate columns)
+  const float* cw;      // [P_pad][32]: (-sum_i y_op, -q_k^T y_op for k >= 1, 0 ...)
+  const float2* table;  // Hermite nodes of -log10 p(|t|): (f, f' / kTabPerUnit)
+  int64_t n_pheno;
+  float df;
+  int32_t q;
+};
+
+struct OutDev {
+  float* r;
+  float* beta;
+  float* se;
+  float* t;
+  float* nl;
+  int64_t ld;
+};
+
+// one 32-column block of the virtual concatenation of all panels' columns
+struct ColBlock {
+  const char* op;  // operand base of this block: chunk ch at op + ch * kBlockBytes
+  int32_t panel;   // owning panel
+  int32_t col0;    // local column of the block's first column (RAW: output column)
+  int32_t ncol;    // valid columns in this block
+  int32_t pad;
+};
+
+struct TailEntry {
+  int64_t row;  // output row (marker - m_begin)
+  int32_t panel;
+  int32_t col;
+  float r;
+  float pad;
+};
+
+struct TailDev {
+  TailEntry* entries;
+  unsigned long long* count;  // [0] = entries requested in the current call
+  int64_t capacity;
+};
+
+struct GemmArgs {
+  const uint8_t* geno;
+  int64_t row_bytes;
+  int64_t m0;        // absolute index of the block's first marker
+  int64_t nm;        // markers in the block
+  int64_t out_row0;  // output row of the block's first marker
+  int32_t n_chunks;
+  int32_t n_cblocks;
+  int32_t n_mtiles;
+  int32_t n_ctiles;
+  int32_t n_panels;
+  int32_t pad0;
+  const ColBlock* cblocks;
+  const PanelDev* panels;
+  const OutDev* outs;
+  const uint4* mlut;     // [nm] decode table of each marker
+  const float* wws;      // [nm][n_panels][32]
+  const float* invh;     // [nm][n_panels]
+  float* raw_out;        // RAW mode destination
+  int64_t raw_ld;
+  TailDev tail;
+};
+
+struct StatsArgs {
+  const uint8_t* geno;
+  int64_t row_bytes;
+  int64_t m0;
+  int64_t nm;
+  int64_t n;           // samples
+  int32_t code;        // tgw_geno_code
+  int32_t prec;        // Prec
+  uint4* mlut;
+  MarkerStat* mstat;
+};
+
+struct BindArgs {
+  OutDev outs[kMaxPanelsPerBind];
+  OutDev* dst;
+  int32_t first;
+  int32_t count;
+};
+
+// ---- launchers (kernels.hip) -------------------------------------------------
+hipError_t launch_qr(const double* C, int64_t ldc, int64_t n, int64_t n_pad, int q, double* X, double* Q,
+                     double* rdiag, int32_t* flags, hipStream_t s);
+hipError_t launch_cov_operands(const double* Q, int64_t n, int64_t n_pad, int q, void* wop_split, void* wop_fp32,
+                               hipStream_t s);
+hipError_t launch_prep(const void* Y, int y_fp64, int64_t ldy, int64_t n, int64_t n_pad, int64_t P,
+                       const double* Q, int q, int prec, void* yop, float* scale, float* invny, float* cw,
+                       int32_t* flags, hipStream_t s);
+hipError_t launch_set_operand(const float* V, int64_t ldv, int64_t n, int64_t n_pad, int64_t P, int prec,
+                              void* yop, hipStream_t s);
+hipError_t launch_table(float2* table, double df, hipStream_t s);
+hipError_t launch_stats(const StatsArgs& a, hipStream_t s);
+hipError_t launch_finalize(const MarkerStat* ms, float* wws, float* invh, int64_t nm, int n_panels,
+                           hipStream_t s);
+hipError_t launch_bind(const BindArgs& a, hipStream_t s);
+hipError_t launch_tail_reset(TailDev t, hipStream_t s);
+hipError_t launch_tail(TailDev t, const PanelDev* panels, const OutDev* outs, hipStream_t s);
+hipError_t launch_debug_stats(const MarkerStat* ms, int64_t nm, double* shift, double* mean, hipStream_t s);
+
+// main contraction; `tile` selects one of the compiled tile shapes
+struct TileShape {
+  int waves;     // waves per workgroup (all along the marker dimension)
+  int wm_frags;  // 32-row fragments per wave
+  int wn_frags;  // 32-column blocks per workgroup tile
+  int tm() const { return waves * wm_frags * 32; }
+  int tp() const { return wn_frags * 32; }
+};
+int n_tile_shapes();
+TileShape tile_shape(int idx);
+// largest resident grid for a tile shape (occupancy x CUs), rounded to 8 XCDs
+int gemm_grid(int idx, int prec, int mode, int n_cu);
+hipError_t launch_gemm(int idx, int prec, int mode, const GemmArgs& a, int grid, hipStream_t s);
+int wgemm_tile();  // tile shape used for the Q^T g contraction
+
+}  // namespace tgw

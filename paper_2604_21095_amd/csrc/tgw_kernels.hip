@@ -1,0 +1,957 @@
+// gfx950 kernels of the phenotype-panel linear association scan.
+//
+//  qr_kernel          FP64 Householder QR of [1 | C] -> Q (Methods 2.2: Q
+//                     spans the covariate space and has orthonormal columns)
+//  prep_kernel        Eq. 1 + column standardization, once per panel, FP64;
+//                     writes the contraction operand (FP32 or BF16 hi + lo)
+//  table_kernel       -log10 p nodes for |t| in [0, 40] at the panel's df
+//  stats_kernel       exact integer per-marker counts -> mean, ||g_c||^2,
+//                     re-centring constant and the 2-bit decode table
+//  gemm_kernel        the contraction of Eq. 2 on the matrix cores with the
+//                     fused epilogue (r, t of Eq. 3, beta, SE, -log10 p)
+//  finalize_kernel    ||g_res||^2 = ||g_c||^2 - sum_k (q_k^T g)^2
+//  tail_kernel        FP64 -log10 p for |t| > 40
+#include "tgw_internal.h"
+
+#include <math.h>
+
+namespace tgw {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+__device__ inline uint32_t bf16_bits_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0u;  // NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+__device__ inline float bf16_to_float(uint32_t b) { return __uint_as_float(b << 16); }
+
+__device__ inline uint32_t pack_bf16x2(float lo, float hi) {
+  return bf16_bits_rne(lo) | (bf16_bits_rne(hi) << 16);
+}
+
+template <int NT>
+__device__ inline double block_sum(double v, double* sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < NT / 64; ++i) s += sh[i];
+  return s;
+}
+
+// reduce NV values at once; sh holds (NT/64) * NV doubles
+template <int NT, int NV>
+__device__ inline void block_sum_vec(double* v, double* sh) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k)
+    for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o);
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) sh[w * NV + k] = v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double s = 0.0;
+    for (int i = 0; i < NT / 64; ++i) s += sh[i * NV + k];
+    v[k] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// operand layout (must match the matrix-core fragment reads in gemm_kernel)
+//
+// BF16 split: block (cb, ch) holds 4096 bf16: [hl][j][lane][e], hl = 0 for
+// hi, 1 for lo; j = K16 step; lane = 32 h + column; e = element.  The sample
+// fed at (j, h, e) is 64 ch + 32 h + 16 (j >> 1) + 4 (j & 1) + (e >> 1) +
+// 8 (e & 1), which is the order in which gemm_kernel decodes packed codes.
+// FP32: block (cb, ch) holds 2048 floats: [j >> 2][lane][j & 3], j = K2 step,
+// sample 64 ch + 32 h + j.
+// ---------------------------------------------------------------------------
+__device__ inline int64_t operand_index_split(int64_t col, int64_t i, int n_chunks, int hl) {
+  const int64_t cb = col >> 5;
+  const int c = (int)(col & 31);
+  const int64_t ch = i >> 6;
+  const int s = (int)(i & 63);
+  const int h = s >> 5;
+  const int rem = s & 31;
+  const int jhi = rem >> 4;
+  const int b = (rem >> 3) & 1;
+  const int jlo = (rem >> 2) & 1;
+  const int d = rem & 3;
+  const int j = 2 * jhi + jlo;
+  const int e = 2 * d + b;
+  const int lane = 32 * h + c;
+  return (cb * n_chunks + ch) * 4096 + hl * 2048 + j * 512 + lane * 8 + e;
+}
+
+__device__ inline int64_t operand_index_fp32(int64_t col, int64_t i, int n_chunks) {
+  const int64_t cb = col >> 5;
+  const int c = (int)(col & 31);
+  const int64_t ch = i >> 6;
+  const int s = (int)(i & 63);
+  const int h = s >> 5;
+  const int j = s & 31;
+  const int lane = 32 * h + c;
+  return (cb * n_chunks + ch) * 2048 + (j >> 2) * 256 + lane * 4 + (j & 3);
+}
+
+__device__ inline void store_operand(void* op, int prec, int64_t col, int64_t i, int n_chunks, double v,
+                                     double* stored) {
+  if (prec == kSplit) {
+    const float f = (float)v;
+    const uint32_t hb = bf16_bits_rne(f);
+    const double hi = (double)bf16_to_float(hb);
+    const uint32_t lb = bf16_bits_rne((float)(v - hi));
+    const double lo = (double)bf16_to_float(lb);
+    uint16_t* p = (uint16_t*)op;
+    p[operand_index_split(col, i, n_chunks, 0)] = (uint16_t)hb;
+    p[operand_index_split(col, i, n_chunks, 1)] = (uint16_t)lb;
+    *stored = hi + lo;
+  } else {
+    const float f = (float)v;
+    ((float*)op)[operand_index_fp32(col, i, n_chunks)] = f;
+    *stored = (double)f;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 Student-t tail: ln of the two-sided p-value
+//   p = I_x(df/2, 1/2), x = df / (df + t^2)
+// I_x(a, b) = x^a (1 - x)^b / (a B(a, b)) * F, F the continued fraction of
+// the incomplete beta function (Abramowitz & Stegun 26.5.8), evaluated with
+// the modified Lentz method; valid for x < (a + 1) / (a + b + 2), otherwise
+// I_x(a, b) = 1 - I_{1-x}(b, a).
+// ---------------------------------------------------------------------------
+__device__ double beta_cf(double x, double a, double b) {
+  const double tiny = 1e-300, eps = 4e-16;
+  double f = tiny, c = tiny, d = 0.0;
+  for (int j = 0; j < 20000; ++j) {
+    double num;
+    if (j == 0) {
+      num = 1.0;
+    } else {
+      const double m = (double)(j >> 1);
+      if (j & 1)
+        num = -(a + m) * (a + b + m) * x / ((a + 2.0 * m) * (a + 2.0 * m + 1.0));
+      else
+        num = m * (b - m) * x / ((a + 2.0 * m - 1.0) * (a + 2.0 * m));
+    }
+    d = 1.0 + num * d;
+    if (fabs(d) < tiny) d = tiny;
+    c = 1.0 + num / c;
+    if (fabs(c) < tiny) c = tiny;
+    d = 1.0 / d;
+    const double del = c * d;
+    f *= del;
+    if (j > 0 && fabs(del - 1.0) < eps) break;
+  }
+  return f;
+}
+
+__device__ double ln_betai_cf(double x, double a, double b) {
+  const double lbeta = lgamma(a) + lgamma(b) - lgamma(a + b);
+  return a * log(x) + b * log1p(-x) - log(a) - lbeta + log(beta_cf(x, a, b));
+}
+
+__device__ double ln_p_two_sided(double t, double df) {
+  t = fabs(t);
+  if (isinf(t)) return -INFINITY;
+  if (t == 0.0) return 0.0;
+  const double a = 0.5 * df, b = 0.5;
+  const double t2 = t * t;
+  const double x = df / (df + t2);
+  const double omx = t2 / (df + t2);
+  if (x < (a + 1.0) / (a + b + 2.0)) return ln_betai_cf(x, a, b);
+  return log1p(-exp(ln_betai_cf(omx, b, a)));
+}
+
+__device__ double ln_pdf_t(double t, double df) {
+  return lgamma(0.5 * (df + 1.0)) - lgamma(0.5 * df) - 0.5 * log(df * M_PI) -
+         0.5 * (df + 1.0) * log1p(t * t / df);
+}
+
+__global__ void table_kernel(float2* table, double df) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= kTabNodes) return;
+  const double t = (double)k / kTabPerUnit;
+  const double lnp = ln_p_two_sided(t, df);
+  const double f = -lnp / M_LN10;
+  const double fp = 2.0 * exp(ln_pdf_t(t, df) - lnp) / M_LN10;  // d(-log10 p)/d|t|
+  table[k] = make_float2((float)f, (float)(fp / kTabPerUnit));
+}
+
+// cubic Hermite interpolation of -log10 p at |t| <= kTMax
+__device__ inline float table_nlog10p(const float2* __restrict__ tab, float at) {
+  const float x = at * (float)kTabPerUnit;
+  int k = (int)x;
+  k = k > kTabNodes - 2 ? kTabNodes - 2 : k;
+  const float s = x - (float)k;
+  const float2 n0 = tab[k], n1 = tab[k + 1];
+  const float s2 = s * s, s3 = s2 * s;
+  const float h00 = 2.f * s3 - 3.f * s2 + 1.f;
+  const float h10 = s3 - 2.f * s2 + s;
+  const float h01 = -2.f * s3 + 3.f * s2;
+  const float h11 = s3 - s2;
+  return n0.x * h00 + n0.y * h10 + n1.x * h01 + n1.y * h11;
+}
+
+// ---------------------------------------------------------------------------
+// covariate QR (one workgroup)
+// X is an (q x n_pad) column-major work copy of [1 | C]; on exit it holds the
+// Householder vectors; Q (q x n_pad) receives the orthonormal basis.
+// ---------------------------------------------------------------------------
+constexpr int kQrThreads = 1024;
+
+__global__ __launch_bounds__(kQrThreads) void qr_kernel(const double* __restrict__ C, int64_t ldc, int64_t n,
+                                                        int64_t n_pad, int q, double* __restrict__ X,
+                                                        double* __restrict__ Q, double* rdiag,
+                                                        int32_t* flags) {
+  __shared__ double sh[kQrThreads / 64];
+  __shared__ double vtv_s[kMaxCov + 1];
+  const int tid = threadIdx.x;
+  // load [1 | C]; pad rows are zero
+  int bad = 0;
+  for (int k = 0; k < q; ++k) {
+    for (int64_t i = tid; i < n_pad; i += kQrThreads) {
+      double v = 0.0;
+      if (i < n) {
+        v = (k == 0) ? 1.0 : C[(int64_t)(k - 1) * ldc + i];
+        if (!isfinite(v)) bad = 1;
+      }
+      X[(int64_t)k * n_pad + i] = v;
+    }
+  }
+  bad = __syncthreads_or(bad);
+  if (bad) {
+    if (tid == 0) flags[0] = 1;
+    return;
+  }
+  for (int j = 0; j < q; ++j) {
+    double* xj = X + (int64_t)j * n_pad;
+    double s = 0.0;
+    for (int64_t i = j + tid; i < n; i += kQrThreads) s += xj[i] * xj[i];
+    s = block_sum<kQrThreads>(s, sh);
+    const double xjj = xj[j];
+    const double nrm = sqrt(s);
+    const double alpha = xjj > 0.0 ? -nrm : nrm;
+    const double v0 = xjj - alpha;
+    const double vtv = s - xjj * xjj + v0 * v0;
+    __syncthreads();
+    if (tid == 0) {
+      xj[j] = v0;
+      rdiag[j] = alpha;
+      vtv_s[j] = vtv;
+    }
+    __syncthreads();
+    for (int k = j + 1; k < q; ++k) {
+      double* xk = X + (int64_t)k * n_pad;
+      double d = 0.0;
+      for (int64_t i = j + tid; i < n; i += kQrThreads) d += xj[i] * xk[i];
+      d = block_sum<kQrThreads>(d, sh);
+      const double f = vtv > 0.0 ? 2.0 * d / vtv : 0.0;
+      for (int64_t i = j + tid; i < n; i += kQrThreads) xk[i] -= f * xj[i];
+      __syncthreads();
+    }
+  }
+  // Q = H_0 ... H_{q-1} [I_q; 0]
+  for (int k = 0; k < q; ++k)
+    for (int64_t i = tid; i < n_pad; i += kQrThreads) Q[(int64_t)k * n_pad + i] = (i == k) ? 1.0 : 0.0;
+  __syncthreads();
+  for (int j = q - 1; j >= 0; --j) {
+    const double* xj = X + (int64_t)j * n_pad;
+    const double vtv = vtv_s[j];
+    for (int k = j; k < q; ++k) {
+      double* qk = Q + (int64_t)k * n_pad;
+      double d = 0.0;
+      for (int64_t i = j + tid; i < n; i += kQrThreads) d += xj[i] * qk[i];
+      d = block_sum<kQrThreads>(d, sh);
+      const double f = vtv > 0.0 ? 2.0 * d / vtv : 0.0;
+      for (int64_t i = j + tid; i < n; i += kQrThreads) qk[i] -= f * xj[i];
+      __syncthreads();
+    }
+  }
+  if (tid == 0) {
+    double mx = 0.0;
+    for (int j = 0; j < q; ++j) mx = fmax(mx, fabs(rdiag[j]));
+    int rd = 0;
+    for (int j = 0; j < q; ++j)
+      if (!(fabs(rdiag[j]) > 1e-10 * mx)) rd = 1;
+    flags[1] = rd;
+  }
+}
+
+// operand blocks of the covariate columns used for Q^T g: slot k <- Q[:, k]
+// for 1 <= k < q, slot 0 and slots >= q are zero.  One 32-column block.
+__global__ void cov_operand_kernel(const double* __restrict__ Q, int64_t n, int64_t n_pad, int q,
+                                   void* wop_split, void* wop_fp32) {
+  const int n_chunks = (int)(n_pad / kChunk);
+  const int64_t total = n_pad * kColBlock;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = idx / kColBlock;
+    const int k = (int)(idx % kColBlock);
+    const double v = (k >= 1 && k < q && i < n) ? Q[(int64_t)k * n_pad + i] : 0.0;
+    double st;
+    store_operand(wop_split, kSplit, k, i, n_chunks, v, &st);
+    store_operand(wop_fp32, kFP32, k, i, n_chunks, v, &st);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// phenotype preparation, one workgroup per column (Eq. 1 + standardization)
+// ---------------------------------------------------------------------------
+constexpr int kPrepThreads = 256;
+
+__global__ __launch_bounds__(kPrepThreads) void prep_kernel(const void* __restrict__ Y, int y_fp64, int64_t ldy,
+                                                            int64_t n, int64_t n_pad, int64_t P,
+                                                            const double* __restrict__ Q, int q, int prec,
+                                                            void* yop, float* scale, float* invny, float* cw,
+                                                            int32_t* flags) {
+  __shared__ double sh[(kPrepThreads / 64) * (kSlots + 2)];
+  __shared__ double qty_s[kSlots];
+  const int64_t p = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int n_chunks = (int)(n_pad / kChunk);
+  const float* yf = (const float*)Y + p * ldy;
+  const double* yd = (const double*)Y + p * ldy;
+  auto yval = [&](int64_t i) -> double { return y_fp64 ? yd[i] : (double)yf[i]; };
+
+  // pass 1: mean (and finiteness)
+  double s = 0.0;
+  int bad = 0;
+  for (int64_t i = tid; i < n; i += kPrepThreads) {
+    const double v = yval(i);
+    if (!isfinite(v)) bad = 1;
+    s += v;
+  }
+  bad = __syncthreads_or(bad);
+  if (bad) {
+    if (tid == 0) atomicOr(flags, 1);
+    return;
+  }
+  const double mean = block_sum<kPrepThreads>(s, sh) / (double)n;
+
+  // pass 2: Q^T y_c and ||y_c||^2
+  double acc[kSlots + 2];
+#pragma unroll
+  for (int k = 0; k < kSlots + 2; ++k) acc[k] = 0.0;
+  for (int64_t i = tid; i < n; i += kPrepThreads) {
+    const double yc = yval(i) - mean;
+    acc[kSlots] += yc * yc;
+#pragma unroll
+    for (int k = 0; k < kSlots; ++k)
+      if (k < q) acc[k] += Q[(int64_t)k * n_pad + i] * yc;
+  }
+  block_sum_vec<kPrepThreads, kSlots + 2>(acc, sh);
+  const double yc2 = acc[kSlots];
+  if (tid < kSlots) qty_s[tid] = acc[tid];
+  __syncthreads();
+
+  // pass 3: ||y_res||^2
+  double r2 = 0.0;
+  for (int64_t i = tid; i < n; i += kPrepThreads) {
+    double v = yval(i) - mean;
+    for (int k = 0; k < q; ++k) v -= Q[(int64_t)k * n_pad + i] * qty_s[k];
+    r2 += v * v;
+  }
+  r2 = block_sum<kPrepThreads>(r2, sh);
+  const double sp = sqrt(r2);
+  const bool valid = sp > 1e-12 * sqrt(yc2);
+  const double inv = valid ? 1.0 / sp : 0.0;
+
+  // pass 4: y~ = y_res / s_p into the operand; accumulate what the stored
+  // (rounded) operand actually holds: sum, norm^2 and Q^T y_op
+#pragma unroll
+  for (int k = 0; k < kSlots + 2; ++k) acc[k] = 0.0;
+  for (int64_t i = tid; i < n; i += kPrepThreads) {
+    double v = yval(i) - mean;
+    for (int k = 0; k < q; ++k) v -= Q[(int64_t)k * n_pad + i] * qty_s[k];
+    double st;
+    store_operand(yop, prec, p, i, n_chunks, v * inv, &st);
+    acc[kSlots] += st;
+    acc[kSlots + 1] += st * st;
+#pragma unroll
+    for (int k = 0; k < kSlots; ++k)
+      if (k < q) acc[k] += Q[(int64_t)k * n_pad + i] * st;
+  }
+  block_sum_vec<kPrepThreads, kSlots + 2>(acc, sh);
+  if (tid == 0) {
+    double proj = 0.0;
+    for (int k = 0; k < q; ++k) proj += acc[k] * acc[k];
+    const double ny2 = acc[kSlots + 1] - proj;
+    scale[p] = (float)sp;
+    invny[p] = (valid && ny2 > 0.0) ? (float)(1.0 / sqrt(ny2)) : __builtin_nanf("");
+  }
+  if (tid < kSlots) {
+    float v = 0.0f;
+    if (tid == 0)
+      v = (float)(-acc[kSlots]);
+    else if (tid < q)
+      v = (float)(-acc[tid]);
+    cw[p * kSlots + tid] = v;
+  }
+}
+
+// test hook: raw operand columns (no centring / scaling)
+__global__ void set_operand_kernel(const float* __restrict__ V, int64_t ldv, int64_t n, int64_t n_pad,
+                                   int64_t P, int prec, void* yop) {
+  const int n_chunks = (int)(n_pad / kChunk);
+  const int64_t total = n_pad * P;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = idx / n_pad;
+    const int64_t i = idx % n_pad;
+    const double v = i < n ? (double)V[p * ldv + i] : 0.0;
+    double st;
+    store_operand(yop, prec, p, i, n_chunks, v, &st);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// per-marker statistics (one wave per marker)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void stats_kernel(StatsArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int64_t m = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (m >= a.nm) return;
+  const uint32_t* row = (const uint32_t*)(a.geno + (a.m0 + m) * a.row_bytes);
+  const int64_t nd = (a.n + 15) / 16;
+  int nmiss = 0, c1 = 0, c2 = 0;
+  for (int64_t d = lane; d < nd; d += 64) {
+    const uint32_t w = row[d];
+    const int64_t nv = a.n - 16 * d;
+    const uint32_t vm = nv >= 16 ? 0xffffffffu : ((1u << (2 * nv)) - 1u);
+    const uint32_t lo = w & 0x55555555u & vm;
+    const uint32_t hi = (w >> 1) & 0x55555555u & vm;
+    uint32_t miss, one, two;
+    if (a.code == 0) {  // dosage: 0,1,2, 3 = missing
+      miss = lo & hi;
+      one = lo & ~hi;
+      two = hi & ~lo;
+    } else {  // PLINK .bed: 0 -> 0, 1 -> missing, 2 -> 1, 3 -> 2
+      miss = lo & ~hi;
+      one = hi & ~lo;
+      two = lo & hi;
+    }
+    nmiss += __popc(miss);
+    c1 += __popc(one);
+    c2 += __popc(two);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    nmiss += __shfl_xor(nmiss, o);
+    c1 += __shfl_xor(c1, o);
+    c2 += __shfl_xor(c2, o);
+  }
+  if (lane != 0) return;
+  const int64_t n_obs = a.n - nmiss;
+  const int64_t sg = c1 + 2 * (int64_t)c2;
+  const int64_t sg2 = c1 + 4 * (int64_t)c2;
+  const int64_t num = n_obs * sg2 - sg * sg;  // n_obs * sum (g - mu)^2
+  const bool ok = n_obs > 0 && num != 0;
+  MarkerStat st;
+  st.flags = ok ? 0 : 1;
+  const double mu = n_obs > 0 ? (double)sg / (double)n_obs : 0.0;
+  const double c = ok ? rint(64.0 * mu) / 64.0 : 0.0;
+  st.mu = mu;
+  st.shift = c;
+  st.gc2 = n_obs > 0 ? (double)num / (double)n_obs : 0.0;
+  st.dmu = (float)(mu - c);
+  // operand value of each 2-bit code, in the coding scheme's code order
+  double val[4];
+  const double vmiss = mu - c;
+  if (a.code == 0) {
+    val[0] = 0.0 - c; val[1] = 1.0 - c; val[2] = 2.0 - c; val[3] = vmiss;
+  } else {
+    val[0] = 0.0 - c; val[1] = vmiss; val[2] = 1.0 - c; val[3] = 2.0 - c;
+  }
+  uint4 lut;
+  if (a.prec == kSplit) {
+    uint32_t lo8 = 0, hi8 = 0;
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t b = bf16_bits_rne((float)val[k]);
+      lo8 |= (b & 0xffu) << (8 * k);
+      hi8 |= (b >> 8) << (8 * k);
+    }
+    lut = make_uint4(lo8, hi8, 0u, 0u);
+  } else {
+    lut = make_uint4(__float_as_uint((float)val[0]), __float_as_uint((float)val[1]),
+                     __float_as_uint((float)val[2]), __float_as_uint((float)val[3]));
+  }
+  a.mlut[m] = lut;
+  a.mstat[m] = st;
+}
+
+__global__ void debug_stats_kernel(const MarkerStat* ms, int64_t nm, double* shift, double* mean) {
+  const int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (m >= nm) return;
+  if (shift) shift[m] = ms[m].shift;
+  if (mean) mean[m] = ms[m].mu;
+}
+
+// ---------------------------------------------------------------------------
+// ||g_res||^2 per (marker, panel) from Q^T g; slot 0 <- mu - c
+// ---------------------------------------------------------------------------
+__global__ void finalize_kernel(const MarkerStat* __restrict__ ms, float* __restrict__ wws,
+                                float* __restrict__ invh, int64_t nm, int n_panels) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= nm * n_panels) return;
+  const int64_t m = idx / n_panels;
+  const MarkerStat st = ms[m];
+  float* ws = wws + idx * kSlots;
+  double h2 = st.gc2;
+  for (int k = 1; k < kSlots; ++k) {
+    const double w = (double)ws[k];
+    h2 -= w * w;
+  }
+  const bool ok = st.flags == 0 && h2 > kMarkerTol * st.gc2;
+  invh[idx] = ok ? (float)(1.0 / sqrt(h2)) : __builtin_nanf("");
+  ws[0] = st.dmu;
+}
+
+// ---------------------------------------------------------------------------
+// per-call output table, tail list
+// ---------------------------------------------------------------------------
+__global__ void bind_kernel(BindArgs a) {
+  const int i = threadIdx.x;
+  if (i < a.count) a.dst[a.first + i] = a.outs[i];
+}
+
+__global__ void tail_reset_kernel(TailDev t) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) t.count[0] = 0ull;
+}
+
+__global__ void tail_kernel(TailDev t, const PanelDev* __restrict__ panels, const OutDev* __restrict__ outs) {
+  const unsigned long long cnt = t.count[0];
+  const int64_t n = cnt < (unsigned long long)t.capacity ? (int64_t)cnt : t.capacity;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const TailEntry e = t.entries[idx];
+    const double df = (double)panels[e.panel].df;
+    const double r = (double)e.r;
+    const double tt = r * sqrt(df / ((1.0 - r) * (1.0 + r)));
+    const double lnp = ln_p_two_sided(tt, df);
+    const OutDev o = outs[e.panel];
+    o.nl[e.row * o.ld + e.col] = (float)(-lnp / M_LN10);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// the contraction (Eq. 2) with the fused epilogue
+//
+// Workgroup tile: TM = NW * WMF * 32 markers x TP = WN * 32 columns; every
+// wave owns WMF 32-row fragments across all WN column blocks.  K loop over
+// 64-sample chunks: the column tile's operand chunk is double-buffered in
+// LDS; each wave reads its markers' packed codes straight from global memory
+// and decodes them in registers with v_perm_b32 and the per-marker table.
+// Persistent: the grid is resident and walks the (marker tile, column tile)
+// list; the list is cut into 8 contiguous ranges, one per XCD (workgroups
+// are dispatched round-robin to XCDs), so that the workgroups of an XCD
+// share column tiles in their L2.
+// ---------------------------------------------------------------------------
+template <int PREC, int NW, int WMF, int WN, int MODE>
+__global__ __launch_bounds__(NW * 64) void gemm_kernel(GemmArgs a) {
+  constexpr int NT = NW * 64;
+  constexpr int TM = NW * WMF * 32;
+  constexpr int TILE_BYTES = WN * kBlockBytes;
+  constexpr int NV4 = TILE_BYTES / 16 / NT;
+  static_assert(TILE_BYTES % (16 * NT) == 0, "tile copy must divide evenly");
+  __shared__ __attribute__((aligned(16))) char lds[2][TILE_BYTES];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int h = lane >> 5;
+  const int r32 = lane & 31;
+
+  const int G = gridDim.x;
+  const int b = blockIdx.x;
+  const int xcd = b & 7;
+  const int slot = b >> 3;
+  const int nslots = G >> 3;
+  const int64_t W = (int64_t)a.n_mtiles * a.n_ctiles;
+  const int64_t wlo = W * xcd / 8;
+  const int64_t whi = W * (xcd + 1) / 8;
+
+  for (int64_t w = wlo + slot; w < whi; w += nslots) {
+    const int ctile = (int)(w / a.n_mtiles);
+    const int mtile = (int)(w - (int64_t)ctile * a.n_mtiles);
+
+    const char* bop[WN];
+#pragma unroll
+    for (int fn = 0; fn < WN; ++fn) {
+      const int cb = ctile * WN + fn;
+      bop[fn] = cb < a.n_cblocks ? a.cblocks[cb].op : nullptr;
+    }
+    const int64_t rowbase = (int64_t)mtile * TM + wave * (WMF * 32);
+    const uint8_t* ap[WMF];
+    uint4 lut[WMF];
+#pragma unroll
+    for (int fm = 0; fm < WMF; ++fm) {
+      int64_t mr = rowbase + fm * 32 + r32;
+      mr = mr < a.nm ? mr : a.nm - 1;
+      ap[fm] = a.geno + (a.m0 + mr) * a.row_bytes + 8 * h;
+      lut[fm] = a.mlut[mr];
+    }
+
+    f32x16 acc[WMF][WN];
+#pragma unroll
+    for (int fm = 0; fm < WMF; ++fm)
+#pragma unroll
+      for (int fn = 0; fn < WN; ++fn)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[fm][fn][i] = 0.0f;
+
+    uint4 breg[NV4];
+    uint2 areg[WMF], anext[WMF];
+    auto load_b = [&](int ch) {
+#pragma unroll
+      for (int v = 0; v < NV4; ++v) {
+        const int f = v * NT + tid;
+        const int fn = f >> 9;  // 512 uint4 per block
+        const int off = (f & 511) * 16;
+        breg[v] = bop[fn] ? *(const uint4*)(bop[fn] + (int64_t)ch * kBlockBytes + off) : make_uint4(0, 0, 0, 0);
+      }
+    };
+    auto store_b = [&](int buf) {
+#pragma unroll
+      for (int v = 0; v < NV4; ++v) {
+        const int f = v * NT + tid;
+        *(uint4*)(&lds[buf][f * 16]) = breg[v];
+      }
+    };
+    auto load_a = [&](int ch, uint2* dst) {
+#pragma unroll
+      for (int fm = 0; fm < WMF; ++fm) dst[fm] = *(const uint2*)(ap[fm] + (int64_t)ch * 16);
+    };
+
+    load_b(0);
+    load_a(0, areg);
+    store_b(0);
+    __syncthreads();
+
+    const int nch = a.n_chunks;
+    for (int ch = 0; ch < nch; ++ch) {
+      const int cur = ch & 1;
+      const bool more = ch + 1 < nch;
+      if (more) {
+        load_b(ch + 1);
+        load_a(ch + 1, anext);
+      }
+      const char* tile = lds[cur];
+      if constexpr (PREC == kSplit) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          bf16x8 A[WMF];
+#pragma unroll
+          for (int fm = 0; fm < WMF; ++fm) {
+            const uint32_t src = (j < 2) ? areg[fm].x : areg[fm].y;
+            u32x4 o;
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+              const int t = 4 * (j & 1) + d;
+              const uint32_t R = (src >> (2 * t)) & 0x00030003u;
+              const uint32_t sel = R * 0x101u + 0x04000400u;
+              o[d] = __builtin_amdgcn_perm(lut[fm].y, lut[fm].x, sel);
+            }
+            A[fm] = __builtin_bit_cast(bf16x8, o);
+          }
+#pragma unroll
+          for (int fn = 0; fn < WN; ++fn) {
+            const char* base = tile + fn * kBlockBytes;
+            const bf16x8 bh = *(const bf16x8*)(base + (j * 512 + lane * 8) * 2);
+            const bf16x8 bl = *(const bf16x8*)(base + (2048 + j * 512 + lane * 8) * 2);
+#pragma unroll
+            for (int fm = 0; fm < WMF; ++fm) {
+              acc[fm][fn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[fm], bh, acc[fm][fn], 0, 0, 0);
+              acc[fm][fn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[fm], bl, acc[fm][fn], 0, 0, 0);
+            }
+          }
+        }
+      } else {
+        uint64_t bits[WMF];
+#pragma unroll
+        for (int fm = 0; fm < WMF; ++fm) bits[fm] = (uint64_t)areg[fm].x | ((uint64_t)areg[fm].y << 32);
+#pragma unroll
+        for (int j4 = 0; j4 < 8; ++j4) {
+          float4 bv[WN];
+#pragma unroll
+          for (int fn = 0; fn < WN; ++fn)
+            bv[fn] = *(const float4*)(tile + fn * kBlockBytes + (j4 * 256 + lane * 4) * 4);
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj) {
+            const int j = j4 * 4 + jj;
+            float av[WMF];
+#pragma unroll
+            for (int fm = 0; fm < WMF; ++fm) {
+              const uint32_t c = (uint32_t)(bits[fm] >> (2 * j)) & 3u;
+              const uint32_t lo = (c & 1u) ? lut[fm].y : lut[fm].x;
+              const uint32_t hi = (c & 1u) ? lut[fm].w : lut[fm].z;
+              av[fm] = __uint_as_float((c & 2u) ? hi : lo);
+            }
+#pragma unroll
+            for (int fn = 0; fn < WN; ++fn) {
+              const float bb = jj == 0 ? bv[fn].x : jj == 1 ? bv[fn].y : jj == 2 ? bv[fn].z : bv[fn].w;
+#pragma unroll
+              for (int fm = 0; fm < WMF; ++fm)
+                acc[fm][fn] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[fm], bb, acc[fm][fn], 0, 0, 0);
+            }
+          }
+        }
+      }
+      if (more) store_b(cur ^ 1);
+      __syncthreads();
+#pragma unroll
+      for (int fm = 0; fm < WMF; ++fm) areg[fm] = anext[fm];
+    }
+
+    // ---------------------------------------------------------------- epilogue
+    if constexpr (MODE == kRaw) {
+#pragma unroll
+      for (int fn = 0; fn < WN; ++fn) {
+        const int cb = ctile * WN + fn;
+        if (cb >= a.n_cblocks) continue;
+        const ColBlock blk = a.cblocks[cb];
+        if (r32 >= blk.ncol) continue;
+#pragma unroll
+        for (int fm = 0; fm < WMF; ++fm)
+#pragma unroll
+          for (int i = 0; i < 16; ++i) {
+            const int64_t mr = rowbase + fm * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
+            if (mr < a.nm) a.raw_out[mr * a.raw_ld + blk.col0 + r32] = acc[fm][fn][i];
+          }
+      }
+    } else {
+      // correction: acc += sum_slot w[m][slot] * cw[p][slot]
+      //   = -(mu - c) sum_i y_op,i - sum_{k>=1} (q_k^T g)(q_k^T y_op)
+      // i.e. the intercept and covariate components of the projection
+      // (I - QQ^T) applied to the stored operand.  Small term: one BF16
+      // matrix-core pass over 32 slots.
+#pragma unroll
+      for (int fn = 0; fn < WN; ++fn) {
+        const int cb = ctile * WN + fn;
+        if (cb >= a.n_cblocks) continue;
+        const ColBlock blk = a.cblocks[cb];
+        const PanelDev pd = a.panels[blk.panel];
+        const float* cwp = pd.cw + (int64_t)(blk.col0 + r32) * kSlots + 8 * h;
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+          const float4 c0 = *(const float4*)(cwp + 16 * ks);
+          const float4 c1 = *(const float4*)(cwp + 16 * ks + 4);
+          u32x4 bo;
+          bo[0] = pack_bf16x2(c0.x, c0.y);
+          bo[1] = pack_bf16x2(c0.z, c0.w);
+          bo[2] = pack_bf16x2(c1.x, c1.y);
+          bo[3] = pack_bf16x2(c1.z, c1.w);
+          const bf16x8 B = __builtin_bit_cast(bf16x8, bo);
+#pragma unroll
+          for (int fm = 0; fm < WMF; ++fm) {
+            int64_t mr = rowbase + fm * 32 + r32;
+            mr = mr < a.nm ? mr : a.nm - 1;
+            const float* wp = a.wws + (mr * a.n_panels + blk.panel) * kSlots + 16 * ks + 8 * h;
+            const float4 w0 = *(const float4*)wp;
+            const float4 w1 = *(const float4*)(wp + 4);
+            u32x4 ao;
+            ao[0] = pack_bf16x2(w0.x, w0.y);
+            ao[1] = pack_bf16x2(w0.z, w0.w);
+            ao[2] = pack_bf16x2(w1.x, w1.y);
+            ao[3] = pack_bf16x2(w1.z, w1.w);
+            acc[fm][fn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ao), B,
+                                                                  acc[fm][fn], 0, 0, 0);
+          }
+        }
+      }
+#pragma unroll
+      for (int fn = 0; fn < WN; ++fn) {
+        const int cb = ctile * WN + fn;
+        if (cb >= a.n_cblocks) continue;
+        const ColBlock blk = a.cblocks[cb];
+        if (r32 >= blk.ncol) continue;
+        const int j = blk.panel;
+        const PanelDev pd = a.panels[j];
+        const OutDev od = a.outs[j];
+        const int64_t p = blk.col0 + r32;
+        const float invny = pd.invny[p];
+        const float sp = pd.scale[p];
+        const float df = pd.df;
+#pragma unroll
+        for (int fm = 0; fm < WMF; ++fm)
+#pragma unroll
+          for (int i = 0; i < 16; ++i) {
+            const int64_t mr = rowbase + fm * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
+            if (mr >= a.nm) continue;
+            const float invh = a.invh[mr * a.n_panels + j];
+            float r = acc[fm][fn][i] * invh * invny;
+            if (r > 1.0f) r = 1.0f;
+            if (r < -1.0f) r = -1.0f;
+            const float omr2 = (1.0f - r) * (1.0f + r);
+            const float t = r * sqrtf(df / omr2);
+            const int64_t o = (a.out_row0 + mr) * od.ld + p;
+            if (od.r) od.r[o] = r;
+            if (od.beta) od.beta[o] = r * sp * invh;
+            if (od.se) od.se[o] = sp * sqrtf(omr2 / df) * invh;
+            if (od.t) od.t[o] = t;
+            if (od.nl) {
+              const float at = fabsf(t);
+              float nl;
+              if (at <= kTMax) {
+                nl = table_nlog10p(pd.table, at);
+              } else if (at != at) {
+                nl = at;  // NaN
+              } else {
+                nl = INFINITY;
+                if (at != INFINITY) {
+                  const unsigned long long idx = atomicAdd(a.tail.count, 1ull);
+                  if (idx < (unsigned long long)a.tail.capacity) {
+                    TailEntry e;
+                    e.row = a.out_row0 + mr;
+                    e.panel = j;
+                    e.col = (int32_t)p;
+                    e.r = r;
+                    e.pad = 0.f;
+                    a.tail.entries[idx] = e;
+                  } else {
+                    nl = table_nlog10p(pd.table, kTMax);  // lower bound
+                  }
+                }
+              }
+              od.nl[o] = nl;
+            }
+          }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// tile shapes and launchers
+// ---------------------------------------------------------------------------
+// {waves, 32-row fragments per wave, 32-column blocks per tile}
+static const TileShape kShapes[] = {
+    {8, 2, 4},  // 512 x 128
+    {4, 2, 4},  // 256 x 128
+    {8, 1, 4},  // 256 x 128, 8 waves
+    {8, 2, 2},  // 512 x 64
+    {8, 2, 1},  // 512 x 32 (Q^T g contraction)
+};
+constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
+constexpr int kWShape = 4;
+
+int n_tile_shapes() { return kNumShapes - 1; }
+TileShape tile_shape(int idx) { return kShapes[idx]; }
+int wgemm_tile() { return kWShape; }
+
+template <int PREC, int MODE>
+static const void* gemm_fn(int idx) {
+  switch (idx) {
+    case 0: return (const void*)gemm_kernel<PREC, 8, 2, 4, MODE>;
+    case 1: return (const void*)gemm_kernel<PREC, 4, 2, 4, MODE>;
+    case 2: return (const void*)gemm_kernel<PREC, 8, 1, 4, MODE>;
+    case 3: return (const void*)gemm_kernel<PREC, 8, 2, 2, MODE>;
+    case 4: return (const void*)gemm_kernel<PREC, 8, 2, 1, MODE>;
+  }
+  return nullptr;
+}
+
+static const void* gemm_fn_any(int idx, int prec, int mode) {
+  if (prec == kSplit) return mode == kRaw ? gemm_fn<kSplit, kRaw>(idx) : gemm_fn<kSplit, kTest>(idx);
+  return mode == kRaw ? gemm_fn<kFP32, kRaw>(idx) : gemm_fn<kFP32, kTest>(idx);
+}
+
+int gemm_grid(int idx, int prec, int mode, int n_cu) {
+  const void* fn = gemm_fn_any(idx, prec, mode);
+  int occ = 0;
+  const int threads = kShapes[idx].waves * 64;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, threads, 0) != hipSuccess || occ < 1) occ = 1;
+  int g = occ * n_cu;
+  g = (g / 8) * 8;
+  return g < 8 ? 8 : g;
+}
+
+hipError_t launch_gemm(int idx, int prec, int mode, const GemmArgs& a, int grid, hipStream_t s) {
+  const void* fn = gemm_fn_any(idx, prec, mode);
+  if (!fn) return hipErrorInvalidValue;
+  const int threads = kShapes[idx].waves * 64;
+  GemmArgs arg = a;
+  void* params[] = {&arg};
+  return hipLaunchKernel(fn, dim3(grid), dim3(threads), params, 0, s);
+}
+
+hipError_t launch_qr(const double* C, int64_t ldc, int64_t n, int64_t n_pad, int q, double* X, double* Q,
+                     double* rdiag, int32_t* flags, hipStream_t s) {
+  hipLaunchKernelGGL(qr_kernel, dim3(1), dim3(kQrThreads), 0, s, C, ldc, n, n_pad, q, X, Q, rdiag, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_cov_operands(const double* Q, int64_t n, int64_t n_pad, int q, void* wop_split, void* wop_fp32,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(cov_operand_kernel, dim3(256), dim3(256), 0, s, Q, n, n_pad, q, wop_split, wop_fp32);
+  return hipGetLastError();
+}
+
+hipError_t launch_prep(const void* Y, int y_fp64, int64_t ldy, int64_t n, int64_t n_pad, int64_t P,
+                       const double* Q, int q, int prec, void* yop, float* scale, float* invny, float* cw,
+                       int32_t* flags, hipStream_t s) {
+  hipLaunchKernelGGL(prep_kernel, dim3((unsigned)P), dim3(kPrepThreads), 0, s, Y, y_fp64, ldy, n, n_pad, P, Q,
+                     q, prec, yop, scale, invny, cw, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_operand(const float* V, int64_t ldv, int64_t n, int64_t n_pad, int64_t P, int prec,
+                              void* yop, hipStream_t s) {
+  hipLaunchKernelGGL(set_operand_kernel, dim3(1024), dim3(256), 0, s, V, ldv, n, n_pad, P, prec, yop);
+  return hipGetLastError();
+}
+
+hipError_t launch_table(float2* table, double df, hipStream_t s) {
+  hipLaunchKernelGGL(table_kernel, dim3((kTabNodes + 255) / 256), dim3(256), 0, s, table, df);
+  return hipGetLastError();
+}
+
+hipError_t launch_stats(const StatsArgs& a, hipStream_t s) {
+  const unsigned blocks = (unsigned)((a.nm + 3) / 4);
+  hipLaunchKernelGGL(stats_kernel, dim3(blocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const MarkerStat* ms, float* wws, float* invh, int64_t nm, int n_panels,
+                           hipStream_t s) {
+  const int64_t total = nm * n_panels;
+  hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, ms, wws, invh, nm,
+                     n_panels);
+  return hipGetLastError();
+}
+
+hipError_t launch_bind(const BindArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(bind_kernel, dim3(1), dim3(kMaxPanelsPerBind), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_tail_reset(TailDev t, hipStream_t s) {
+  hipLaunchKernelGGL(tail_reset_kernel, dim3(1), dim3(64), 0, s, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_tail(TailDev t, const PanelDev* panels, const OutDev* outs, hipStream_t s) {
+  hipLaunchKernelGGL(tail_kernel, dim3(64), dim3(64), 0, s, t, panels, outs);
+  return hipGetLastError();
+}
+
+hipError_t launch_debug_stats(const MarkerStat* ms, int64_t nm, double* shift, double* mean, hipStream_t s) {
+  hipLaunchKernelGGL(debug_stats_kernel, dim3((unsigned)((nm + 255) / 256)), dim3(256), 0, s, ms, nm, shift, mean);
+  return hipGetLastError();
+}
+
+}  // namespace tgw

@@ -1,0 +1,885 @@
+// Host runtime behind the C ABI in include/tgw.h: handles, argument checks,
+// workspace, the per-block launch sequence, autotuner and graph capture.
+#include "../../include/tgw.h"
+#include "tgw_internal.h"
+
+#include <algorithm>
+#include <cerrno>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <sys/stat.h>
+#include <vector>
+
+using namespace tgw;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static tgw_status fail(tgw_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+static tgw_status hip_fail(hipError_t e, const char* what) {
+  return fail(e == hipErrorOutOfMemory ? TGW_ERR_OUT_OF_MEMORY : TGW_ERR_DEVICE,
+              std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr)                                   \
+  do {                                                  \
+    hipError_t _e = (expr);                             \
+    if (_e != hipSuccess) return hip_fail(_e, #expr);   \
+  } while (0)
+
+#define TGW_GUARD_BEGIN try {
+#define TGW_GUARD_END                                                  \
+  }                                                                    \
+  catch (const std::bad_alloc&) {                                      \
+    return fail(TGW_ERR_OUT_OF_MEMORY, "host allocation failed");      \
+  }                                                                    \
+  catch (const std::exception& ex) {                                   \
+    return fail(TGW_ERR_DEVICE, std::string("internal error: ") + ex.what()); \
+  }                                                                    \
+  catch (...) {                                                        \
+    return fail(TGW_ERR_DEVICE, "internal error");                     \
+  }
+
+// ---------------------------------------------------------------------------
+// device properties
+// ---------------------------------------------------------------------------
+struct DevInfo {
+  int n_cu = 0;
+  std::string arch;
+  bool gfx950 = false;
+};
+
+static std::mutex g_dev_mu;
+static std::map<int, DevInfo> g_dev;
+
+static tgw_status device_info(int* dev_out, DevInfo* info) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_dev_mu);
+  auto it = g_dev.find(dev);
+  if (it == g_dev.end()) {
+    hipDeviceProp_t p;
+    HIP_TRY(hipGetDeviceProperties(&p, dev));
+    DevInfo d;
+    d.n_cu = p.multiProcessorCount;
+    d.arch = p.gcnArchName;
+    d.gfx950 = d.arch.rfind("gfx950", 0) == 0;
+    it = g_dev.emplace(dev, d).first;
+  }
+  if (!it->second.gfx950)
+    return fail(TGW_ERR_UNSUPPORTED, "device architecture " + it->second.arch + " is not gfx950");
+  if (dev_out) *dev_out = dev;
+  if (info) *info = it->second;
+  return TGW_OK;
+}
+
+static int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+template <class T>
+static hipError_t dmalloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  return hipMalloc((void**)p, count * sizeof(T));
+}
+
+// ---------------------------------------------------------------------------
+// handles
+// ---------------------------------------------------------------------------
+struct tgw_covariates {
+  int device = 0;
+  int64_t n = 0, n_pad = 0;
+  int q = 0, n_chunks = 0;
+  double* Q = nullptr;       // [q][n_pad]
+  void* wop[2] = {nullptr, nullptr};  // Q^T g operand block: [kFP32], [kSplit]
+};
+
+struct tgw_panel {
+  const tgw_covariates* cov = nullptr;
+  int64_t P = 0, P_pad = 0;
+  int prec = 0;
+  int64_t df = 0;
+  void* yop = nullptr;
+  float* scale = nullptr;
+  float* invny = nullptr;
+  float* cw = nullptr;
+  float2* table = nullptr;
+};
+
+struct tgw_plan {
+  std::vector<const tgw_panel*> panels;
+  int device = 0, prec = 0, n_cu = 0;
+  std::string arch;
+  int64_t n = 0, n_pad = 0;
+  int n_chunks = 0, n_panels = 0, n_cb = 0;
+  int64_t MB = 0;
+  ColBlock* d_cb_main = nullptr;
+  ColBlock* d_cb_w = nullptr;
+  PanelDev* d_panels = nullptr;
+  OutDev* d_outs = nullptr;
+  uint4* mlut = nullptr;
+  MarkerStat* mstat = nullptr;
+  float* wws = nullptr;
+  float* invh = nullptr;
+  TailEntry* tail_entries = nullptr;
+  unsigned long long* tail_count = nullptr;
+  int64_t tail_cap = 0;
+  int tile = 0;
+  std::vector<int> grid_main;  // per tile shape
+  int grid_w = 0;
+  bool profile = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
+};
+
+struct tgw_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+// ---------------------------------------------------------------------------
+// library
+// ---------------------------------------------------------------------------
+extern "C" const char* tgw_status_string(tgw_status s) {
+  switch (s) {
+    case TGW_OK: return "ok";
+    case TGW_ERR_INVALID_ARG: return "invalid argument";
+    case TGW_ERR_SHAPE: return "inconsistent shape";
+    case TGW_ERR_RANK_DEFICIENT: return "covariates rank deficient";
+    case TGW_ERR_NONFINITE: return "non-finite input";
+    case TGW_ERR_DEVICE: return "device error";
+    case TGW_ERR_OUT_OF_MEMORY: return "out of memory";
+    case TGW_ERR_UNSUPPORTED: return "unsupported";
+    case TGW_ERR_TAIL_OVERFLOW: return "tail list overflow";
+  }
+  return "unknown status";
+}
+
+extern "C" const char* tgw_last_error(void) { return g_err.c_str(); }
+extern "C" int32_t tgw_abi_version(void) { return TGW_ABI_VERSION; }
+
+extern "C" tgw_status tgw_init(void) {
+  TGW_GUARD_BEGIN
+  return device_info(nullptr, nullptr);
+  TGW_GUARD_END
+}
+
+extern "C" tgw_status tgw_tile_shape(int32_t idx, int32_t* tile_markers, int32_t* tile_cols, int32_t* waves) {
+  if (idx < 0 || idx >= n_tile_shapes()) return fail(TGW_ERR_INVALID_ARG, "tile index out of range");
+  const TileShape s = tile_shape(idx);
+  if (tile_markers) *tile_markers = s.tm();
+  if (tile_cols) *tile_cols = s.tp();
+  if (waves) *waves = s.waves;
+  return TGW_OK;
+}
+
+// ---------------------------------------------------------------------------
+// covariates
+// ---------------------------------------------------------------------------
+extern "C" void tgw_covariates_free(tgw_covariates* cov) {
+  if (!cov) return;
+  (void)hipFree(cov->Q);
+  (void)hipFree(cov->wop[0]);
+  (void)hipFree(cov->wop[1]);
+  delete cov;
+}
+
+extern "C" tgw_status tgw_fit_covariates(int64_t n_samples, int32_t n_cov, const double* d_C, int64_t ldc,
+                                         void* stream, tgw_covariates** out) {
+  TGW_GUARD_BEGIN
+  if (!out) return fail(TGW_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (n_cov < 0 || n_cov > kMaxCov) return fail(TGW_ERR_SHAPE, "n_cov must be in [0, 31]");
+  if (n_samples < (int64_t)n_cov + 3) return fail(TGW_ERR_SHAPE, "n_samples must be >= n_cov + 3");
+  if (n_cov > 0 && !d_C) return fail(TGW_ERR_INVALID_ARG, "d_C is NULL");
+  if (n_cov > 0 && ldc < n_samples) return fail(TGW_ERR_SHAPE, "ldc < n_samples");
+  int dev;
+  tgw_status st = device_info(&dev, nullptr);
+  if (st != TGW_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  auto* cov = new tgw_covariates();
+  cov->device = dev;
+  cov->n = n_samples;
+  cov->n_pad = round_up(n_samples, kChunk);
+  cov->q = n_cov + 1;
+  cov->n_chunks = (int)(cov->n_pad / kChunk);
+  double *X = nullptr, *rdiag = nullptr;
+  int32_t* flags = nullptr;
+  auto cleanup = [&]() {
+    (void)hipFree(X);
+    (void)hipFree(rdiag);
+    (void)hipFree(flags);
+  };
+  hipError_t e = dmalloc(&cov->Q, (size_t)cov->q * cov->n_pad);
+  if (e == hipSuccess) e = dmalloc(&X, (size_t)cov->q * cov->n_pad);
+  if (e == hipSuccess) e = dmalloc(&rdiag, (size_t)cov->q);
+  if (e == hipSuccess) e = dmalloc(&flags, 2);
+  if (e == hipSuccess) e = hipMalloc(&cov->wop[kFP32], (size_t)cov->n_chunks * kBlockBytes);
+  if (e == hipSuccess) e = hipMalloc(&cov->wop[kSplit], (size_t)cov->n_chunks * kBlockBytes);
+  if (e == hipSuccess) e = hipMemsetAsync(flags, 0, 2 * sizeof(int32_t), s);
+  if (e == hipSuccess) e = launch_qr(d_C, ldc, n_samples, cov->n_pad, cov->q, X, cov->Q, rdiag, flags, s);
+  if (e == hipSuccess)
+    e = launch_cov_operands(cov->Q, n_samples, cov->n_pad, cov->q, cov->wop[kSplit], cov->wop[kFP32], s);
+  int32_t hf[2] = {0, 0};
+  if (e == hipSuccess) e = hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  cleanup();
+  if (e != hipSuccess) {
+    tgw_covariates_free(cov);
+    return hip_fail(e, "tgw_fit_covariates");
+  }
+  if (hf[0]) {
+    tgw_covariates_free(cov);
+    return fail(TGW_ERR_NONFINITE, "covariates contain NaN or Inf");
+  }
+  if (hf[1]) {
+    tgw_covariates_free(cov);
+    return fail(TGW_ERR_RANK_DEFICIENT, "[1 | C] is rank deficient");
+  }
+  *out = cov;
+  return TGW_OK;
+  TGW_GUARD_END
+}
+
+extern "C" tgw_status tgw_covariates_q(const tgw_covariates* cov, double* d_Q, int64_t ldq, void* stream) {
+  TGW_GUARD_BEGIN
+  if (!cov || !d_Q) return fail(TGW_ERR_INVALID_ARG, "NULL argument");
+  if (ldq < cov->n) return fail(TGW_ERR_SHAPE, "ldq < n");
+  HIP_TRY(hipMemcpy2DAsync(d_Q, ldq * sizeof(double), cov->Q, cov->n_pad * sizeof(double),
+                           cov->n * sizeof(double), cov->q, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return TGW_OK;
+  TGW_GUARD_END
+}
+
+// ---------------------------------------------------------------------------
+// panels
+// ---------------------------------------------------------------------------
+extern "C" void tgw_panel_free(tgw_panel* p) {
+  if (!p) return;
+  (void)hipFree(p->yop);
+  (void)hipFree(p->scale);
+  (void)hipFree(p->invny);
+  (void)hipFree(p->cw);
+  (void)hipFree(p->table);
+  delete p;
+}
+
+extern "C" tgw_status tgw_prepare_phenotypes(const tgw_covariates* cov, int64_t n_pheno, const void* d_Y,
+                                             int32_t y_is_fp64, int64_t ldy, tgw_precision prec, void* stream,
+                                             tgw_panel** out) {
+  TGW_GUARD_BEGIN
+  if (!out) return fail(TGW_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!cov || !d_Y) return fail(TGW_ERR_INVALID_ARG, "NULL argument");
+  if (prec != TGW_PREC_FP32 && prec != TGW_PREC_SPLIT) return fail(TGW_ERR_INVALID_ARG, "bad precision");
+  if (y_is_fp64 != 0 && y_is_fp64 != 1) return fail(TGW_ERR_INVALID_ARG, "y_is_fp64 must be 0 or 1");
+  if (n_pheno < 1) return fail(TGW_ERR_SHAPE, "n_pheno must be >= 1");
+  if (ldy < cov->n) return fail(TGW_ERR_SHAPE, "ldy < n_samples");
+  int dev;
+  tgw_status st = device_info(&dev, nullptr);
+  if (st != TGW_OK) return st;
+  if (dev != cov->device) return fail(TGW_ERR_INVALID_ARG, "covariates live on another device");
+  hipStream_t s = (hipStream_t)stream;
+  auto* p = new tgw_panel();
+  p->cov = cov;
+  p->P = n_pheno;
+  p->P_pad = round_up(n_pheno, kColBlock);
+  p->prec = prec == TGW_PREC_SPLIT ? kSplit : kFP32;
+  p->df = cov->n - cov->q - 1;
+  int32_t* flags = nullptr;
+  const size_t op_bytes = (size_t)(p->P_pad / kColBlock) * cov->n_chunks * kBlockBytes;
+  hipError_t e = hipMalloc(&p->yop, op_bytes);
+  if (e == hipSuccess) e = dmalloc(&p->scale, p->P_pad);
+  if (e == hipSuccess) e = dmalloc(&p->invny, p->P_pad);
+  if (e == hipSuccess) e = dmalloc(&p->cw, (size_t)p->P_pad * kSlots);
+  if (e == hipSuccess) e = dmalloc(&p->table, kTabNodes);
+  if (e == hipSuccess) e = dmalloc(&flags, 1);
+  if (e == hipSuccess) e = hipMemsetAsync(p->yop, 0, op_bytes, s);
+  if (e == hipSuccess) e = hipMemsetAsync(p->scale, 0, p->P_pad * sizeof(float), s);
+  if (e == hipSuccess) e = hipMemsetAsync(p->invny, 0, p->P_pad * sizeof(float), s);
+  if (e == hipSuccess) e = hipMemsetAsync(p->cw, 0, p->P_pad * kSlots * sizeof(float), s);
+  if (e == hipSuccess) e = hipMemsetAsync(flags, 0, sizeof(int32_t), s);
+  if (e == hipSuccess)
+    e = launch_prep(d_Y, y_is_fp64, ldy, cov->n, cov->n_pad, n_pheno, cov->Q, cov->q, p->prec, p->yop, p->scale,
+                    p->invny, p->cw, flags, s);
+  if (e == hipSuccess) e = launch_table(p->table, (double)p->df, s);
+  int32_t hf = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(flags);
+  if (e != hipSuccess) {
+    tgw_panel_free(p);
+    return hip_fail(e, "tgw_prepare_phenotypes");
+  }
+  if (hf) {
+    tgw_panel_free(p);
+    return fail(TGW_ERR_NONFINITE, "phenotypes contain NaN or Inf");
+  }
+  *out = p;
+  return TGW_OK;
+  TGW_GUARD_END
+}
+
+extern "C" tgw_status tgw_panel_info(const tgw_panel* p, int64_t* n, int64_t* np, int32_t* q, int64_t* df) {
+  if (!p) return fail(TGW_ERR_INVALID_ARG, "panel is NULL");
+  if (n) *n = p->cov->n;
+  if (np) *np = p->P;
+  if (q) *q = p->cov->q;
+  if (df) *df = p->df;
+  return TGW_OK;
+}
+
+extern "C" tgw_status tgw_debug_set_operand(tgw_panel* p, const float* d_V, int64_t ldv, void* stream) {
+  TGW_GUARD_BEGIN
+  if (!p || !d_V) return fail(TGW_ERR_INVALID_ARG, "NULL argument");
+  if (ldv < p->cov->n) return fail(TGW_ERR_SHAPE, "ldv < n");
+  HIP_TRY(launch_set_operand(d_V, ldv, p->cov->n, p->cov->n_pad, p->P, p->prec, p->yop, (hipStream_t)stream));
+  return TGW_OK;
+  TGW_GUARD_END
+}
+
+// ---------------------------------------------------------------------------
+// plans
+// ---------------------------------------------------------------------------
+extern "C" void tgw_plan_free(tgw_plan* pl) {
+  if (!pl) return;
+  for (auto& ev : pl->prof_events) {
+    (void)hipEventDestroy(ev.first);
+    (void)hipEventDestroy(ev.second);
+  }
+  (void)hipFree(pl->d_cb_main);
+  (void)hipFree(pl->d_cb_w);
+  (void)hipFree(pl->d_panels);
+  (void)hipFree(pl->d_outs);
+  (void)hipFree(pl->mlut);
+  (void)hipFree(pl->mstat);
+  (void)hipFree(pl->wws);
+  (void)hipFree(pl->invh);
+  (void)hipFree(pl->tail_entries);
+  (void)hipFree(pl->tail_count);
+  delete pl;
+}
+
+static std::string tune_key(const tgw_plan* pl) {
+  char buf[160];
+  snprintf(buf, sizeof(buf), "%s/npad%lld/cb%d/np%d/prec%d", pl->arch.c_str(), (long long)pl->n_pad, pl->n_cb,
+           pl->n_panels, pl->prec);
+  return buf;
+}
+
+static std::string tune_cache_path() {
+  const char* env = getenv("TGW_TUNE_CACHE");
+  if (env && *env) return env;
+  const char* home = getenv("HOME");
+  return std::string(home ? home : "/tmp") + "/.cache/tgw/tune.json";
+}
+
+// the cache is a flat JSON object {"key": tile, ...}
+static std::map<std::string, int> tune_cache_read() {
+  std::map<std::string, int> m;
+  FILE* f = fopen(tune_cache_path().c_str(), "r");
+  if (!f) return m;
+  std::string s;
+  char buf[4096];
+  size_t k;
+  while ((k = fread(buf, 1, sizeof(buf), f)) > 0) s.append(buf, k);
+  fclose(f);
+  size_t pos = 0;
+  while (true) {
+    size_t a = s.find('"', pos);
+    if (a == std::string::npos) break;
+    size_t b = s.find('"', a + 1);
+    if (b == std::string::npos) break;
+    size_t c = s.find(':', b);
+    if (c == std::string::npos) break;
+    m[s.substr(a + 1, b - a - 1)] = atoi(s.c_str() + c + 1);
+    pos = c + 1;
+  }
+  return m;
+}
+
+static void tune_cache_write(const std::string& key, int tile) {
+  auto m = tune_cache_read();
+  m[key] = tile;
+  const std::string path = tune_cache_path();
+  for (size_t i = 1; i < path.size(); ++i)
+    if (path[i] == '/') mkdir(path.substr(0, i).c_str(), 0755);
+  const std::string tmp = path + ".tmp";
+  FILE* f = fopen(tmp.c_str(), "w");
+  if (!f) return;
+  fputs("{\n", f);
+  size_t i = 0;
+  for (auto& kv : m) fprintf(f, "  \"%s\": %d%s\n", kv.first.c_str(), kv.second, ++i < m.size() ? "," : "");
+  fputs("}\n", f);
+  fclose(f);
+  rename(tmp.c_str(), path.c_str());
+}
+
+extern "C" tgw_status tgw_plan_create(const tgw_panel* const* panels, int32_t n_panels,
+                                      const tgw_plan_options* opts, tgw_plan** out) {
+  TGW_GUARD_BEGIN
+  if (!out) return fail(TGW_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!panels || n_panels < 1) return fail(TGW_ERR_INVALID_ARG, "need at least one panel");
+  for (int j = 0; j < n_panels; ++j)
+    if (!panels[j]) return fail(TGW_ERR_INVALID_ARG, "NULL panel");
+  const tgw_panel* p0 = panels[0];
+  for (int j = 1; j < n_panels; ++j) {
+    if (panels[j]->cov->n != p0->cov->n) return fail(TGW_ERR_SHAPE, "panels differ in n_samples");
+    if (panels[j]->prec != p0->prec) return fail(TGW_ERR_INVALID_ARG, "panels differ in precision");
+    if (panels[j]->cov->device != p0->cov->device) return fail(TGW_ERR_INVALID_ARG, "panels on different devices");
+  }
+  int dev;
+  DevInfo info;
+  tgw_status st = device_info(&dev, &info);
+  if (st != TGW_OK) return st;
+  if (dev != p0->cov->device) return fail(TGW_ERR_INVALID_ARG, "current device differs from the panels'");
+  tgw_plan_options o{};
+  if (opts) o = *opts;
+  if (o.block_markers < 0 || o.tail_capacity < 0) return fail(TGW_ERR_INVALID_ARG, "negative option");
+  if (o.tile >= n_tile_shapes()) return fail(TGW_ERR_INVALID_ARG, "tile index out of range");
+
+  auto* pl = new tgw_plan();
+  pl->panels.assign(panels, panels + n_panels);
+  pl->device = dev;
+  pl->n_cu = info.n_cu;
+  pl->arch = info.arch;
+  pl->prec = p0->prec;
+  pl->n = p0->cov->n;
+  pl->n_pad = p0->cov->n_pad;
+  pl->n_chunks = p0->cov->n_chunks;
+  pl->n_panels = n_panels;
+
+  std::vector<ColBlock> cbm, cbw;
+  std::vector<PanelDev> pdv;
+  for (int j = 0; j < n_panels; ++j) {
+    const tgw_panel* p = panels[j];
+    const int64_t nb = p->P_pad / kColBlock;
+    for (int64_t b = 0; b < nb; ++b) {
+      ColBlock c{};
+      c.op = (const char*)p->yop + (size_t)b * pl->n_chunks * kBlockBytes;
+      c.panel = j;
+      c.col0 = (int32_t)(b * kColBlock);
+      c.ncol = (int32_t)std::min<int64_t>(kColBlock, p->P - b * kColBlock);
+      cbm.push_back(c);
+    }
+    ColBlock w{};
+    w.op = (const char*)p->cov->wop[pl->prec];
+    w.panel = j;
+    w.col0 = j * kSlots;
+    w.ncol = kSlots;
+    cbw.push_back(w);
+    PanelDev d{};
+    d.scale = p->scale;
+    d.invny = p->invny;
+    d.cw = p->cw;
+    d.table = p->table;
+    d.n_pheno = p->P;
+    d.df = (float)p->df;
+    d.q = p->cov->q;
+    pdv.push_back(d);
+  }
+  pl->n_cb = (int)cbm.size();
+  const int64_t per_marker = (int64_t)sizeof(uint4) + sizeof(MarkerStat) + (int64_t)n_panels * (kSlots + 1) * 4;
+  int64_t MB = o.block_markers;
+  if (MB == 0) MB = std::max<int64_t>(4096, std::min<int64_t>(1 << 20, (2ll << 30) / per_marker));
+  MB = round_up(MB, 512);
+  pl->MB = MB;
+  pl->tail_cap = o.tail_capacity ? o.tail_capacity : (1 << 20);
+
+  hipError_t e = dmalloc(&pl->d_cb_main, cbm.size());
+  if (e == hipSuccess) e = dmalloc(&pl->d_cb_w, cbw.size());
+  if (e == hipSuccess) e = dmalloc(&pl->d_panels, pdv.size());
+  if (e == hipSuccess) e = dmalloc(&pl->d_outs, (size_t)n_panels);
+  if (e == hipSuccess) e = dmalloc(&pl->mlut, (size_t)MB);
+  if (e == hipSuccess) e = dmalloc(&pl->mstat, (size_t)MB);
+  if (e == hipSuccess) e = dmalloc(&pl->wws, (size_t)MB * n_panels * kSlots);
+  if (e == hipSuccess) e = dmalloc(&pl->invh, (size_t)MB * n_panels);
+  if (e == hipSuccess) e = dmalloc(&pl->tail_entries, (size_t)pl->tail_cap);
+  if (e == hipSuccess) e = dmalloc(&pl->tail_count, 1);
+  if (e == hipSuccess) e = hipMemcpy(pl->d_cb_main, cbm.data(), cbm.size() * sizeof(ColBlock), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(pl->d_cb_w, cbw.data(), cbw.size() * sizeof(ColBlock), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(pl->d_panels, pdv.data(), pdv.size() * sizeof(PanelDev), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(pl->d_outs, 0, n_panels * sizeof(OutDev));
+  if (e == hipSuccess) e = hipMemset(pl->tail_count, 0, sizeof(unsigned long long));
+  if (e != hipSuccess) {
+    tgw_plan_free(pl);
+    return hip_fail(e, "tgw_plan_create");
+  }
+  for (int i = 0; i < n_tile_shapes(); ++i) pl->grid_main.push_back(gemm_grid(i, pl->prec, kTest, pl->n_cu));
+  pl->grid_w = gemm_grid(wgemm_tile(), pl->prec, kRaw, pl->n_cu);
+  if (o.tile >= 0) {
+    pl->tile = o.tile;
+  } else {
+    auto cache = tune_cache_read();
+    auto it = cache.find(tune_key(pl));
+    pl->tile = (it != cache.end() && it->second >= 0 && it->second < n_tile_shapes()) ? it->second : 0;
+  }
+  *out = pl;
+  return TGW_OK;
+  TGW_GUARD_END
+}
+
+extern "C" tgw_status tgw_plan_info(const tgw_plan* pl, int32_t* tile, int32_t* n_tiles, int64_t* block_markers) {
+  if (!pl) return fail(TGW_ERR_INVALID_ARG, "plan is NULL");
+  if (tile) *tile = pl->tile;
+  if (n_tiles) *n_tiles = n_tile_shapes();
+  if (block_markers) *block_markers = pl->MB;
+  return TGW_OK;
+}
+
+// ---------------------------------------------------------------------------
+// the scan
+// ---------------------------------------------------------------------------
+struct ScanCall {
+  const uint8_t* geno;
+  int64_t n_markers, row_bytes;
+  int code;
+  int64_t m_begin, m_end;
+  const tgw_outputs* outs;
+};
+
+static tgw_status check_call(const tgw_plan* pl, const ScanCall& c, bool need_outs) {
+  if (!pl) return fail(TGW_ERR_INVALID_ARG, "plan is NULL");
+  if (!c.geno) return fail(TGW_ERR_INVALID_ARG, "d_geno is NULL");
+  if (((uintptr_t)c.geno & 15) != 0) return fail(TGW_ERR_SHAPE, "d_geno must be 16-byte aligned");
+  if (c.code != TGW_CODE_DOSAGE && c.code != TGW_CODE_PLINK_BED) return fail(TGW_ERR_INVALID_ARG, "bad code");
+  if (c.row_bytes <= 0 || c.row_bytes % 16 != 0) return fail(TGW_ERR_SHAPE, "row_bytes must be a positive multiple of 16");
+  if (c.row_bytes < pl->n_pad / 4) return fail(TGW_ERR_SHAPE, "row_bytes < 16 * ceil(n_samples / 64)");
+  if (c.n_markers < 0 || c.m_begin < 0 || c.m_begin > c.m_end || c.m_end > c.n_markers)
+    return fail(TGW_ERR_SHAPE, "need 0 <= m_begin <= m_end <= n_markers");
+  if (need_outs) {
+    if (!c.outs) return fail(TGW_ERR_INVALID_ARG, "outs is NULL");
+    for (int j = 0; j < pl->n_panels; ++j) {
+      const tgw_outputs& o = c.outs[j];
+      const bool any = o.r || o.beta || o.se || o.t || o.nlog10p;
+      if (any && o.ld < pl->panels[j]->P) return fail(TGW_ERR_SHAPE, "outs[j].ld < n_pheno of panel j");
+    }
+  }
+  return TGW_OK;
+}
+
+static GemmArgs base_args(const tgw_plan* pl, const ScanCall& c, int64_t m0, int64_t nm) {
+  GemmArgs a{};
+  a.geno = c.geno;
+  a.row_bytes = c.row_bytes;
+  a.m0 = m0;
+  a.nm = nm;
+  a.out_row0 = m0 - c.m_begin;
+  a.n_chunks = pl->n_chunks;
+  a.n_panels = pl->n_panels;
+  a.panels = pl->d_panels;
+  a.outs = pl->d_outs;
+  a.mlut = pl->mlut;
+  a.wws = pl->wws;
+  a.invh = pl->invh;
+  a.tail.entries = pl->tail_entries;
+  a.tail.count = pl->tail_count;
+  a.tail.capacity = pl->tail_cap;
+  return a;
+}
+
+// per-block preamble: integer stats, Q^T g, ||g_res||
+static hipError_t enqueue_block_stats(tgw_plan* pl, const ScanCall& c, int64_t m0, int64_t nm, hipStream_t s) {
+  StatsArgs sa{};
+  sa.geno = c.geno;
+  sa.row_bytes = c.row_bytes;
+  sa.m0 = m0;
+  sa.nm = nm;
+  sa.n = pl->n;
+  sa.code = c.code;
+  sa.prec = pl->prec;
+  sa.mlut = pl->mlut;
+  sa.mstat = pl->mstat;
+  hipError_t e = launch_stats(sa, s);
+  if (e != hipSuccess) return e;
+  GemmArgs a = base_args(pl, c, m0, nm);
+  const TileShape ws = tile_shape(wgemm_tile());
+  a.cblocks = pl->d_cb_w;
+  a.n_cblocks = pl->n_panels;
+  a.n_ctiles = (int)((pl->n_panels + ws.wn_frags - 1) / ws.wn_frags);
+  a.n_mtiles = (int)((nm + ws.tm() - 1) / ws.tm());
+  a.raw_out = pl->wws;
+  a.raw_ld = (int64_t)pl->n_panels * kSlots;
+  e = launch_gemm(wgemm_tile(), pl->prec, kRaw, a, pl->grid_w, s);
+  if (e != hipSuccess) return e;
+  return launch_finalize(pl->mstat, pl->wws, pl->invh, nm, pl->n_panels, s);
+}
+
+static hipError_t enqueue_main(tgw_plan* pl, const ScanCall& c, int64_t m0, int64_t nm, int tile, hipStream_t s) {
+  GemmArgs a = base_args(pl, c, m0, nm);
+  const TileShape ts = tile_shape(tile);
+  a.cblocks = pl->d_cb_main;
+  a.n_cblocks = pl->n_cb;
+  a.n_ctiles = (pl->n_cb + ts.wn_frags - 1) / ts.wn_frags;
+  a.n_mtiles = (int)((nm + ts.tm() - 1) / ts.tm());
+  if (!pl->profile) return launch_gemm(tile, pl->prec, kTest, a, pl->grid_main[tile], s);
+  hipEvent_t e0, e1;
+  hipError_t e = hipEventCreate(&e0);
+  if (e != hipSuccess) return e;
+  e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return e;
+  }
+  pl->prof_events.emplace_back(e0, e1);
+  e = hipEventRecord(e0, s);
+  if (e == hipSuccess) e = launch_gemm(tile, pl->prec, kTest, a, pl->grid_main[tile], s);
+  if (e == hipSuccess) e = hipEventRecord(e1, s);
+  return e;
+}
+
+static hipError_t enqueue_bind(tgw_plan* pl, const tgw_outputs* outs, hipStream_t s) {
+  for (int j0 = 0; j0 < pl->n_panels; j0 += kMaxPanelsPerBind) {
+    BindArgs b{};
+    b.dst = pl->d_outs;
+    b.first = j0;
+    b.count = std::min(kMaxPanelsPerBind, pl->n_panels - j0);
+    for (int i = 0; i < b.count; ++i) {
+      const tgw_outputs& o = outs[j0 + i];
+      b.outs[i] = OutDev{o.r, o.beta, o.se, o.t, o.nlog10p, o.ld};
+    }
+    hipError_t e = launch_bind(b, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+static hipError_t enqueue_scan(tgw_plan* pl, const ScanCall& c, hipStream_t s) {
+  hipError_t e = enqueue_bind(pl, c.outs, s);
+  if (e == hipSuccess) e = launch_tail_reset(TailDev{pl->tail_entries, pl->tail_count, pl->tail_cap}, s);
+  for (int64_t m0 = c.m_begin; e == hipSuccess && m0 < c.m_end; m0 += pl->MB) {
+    const int64_t nm = std::min(pl->MB, c.m_end - m0);
+    e = enqueue_block_stats(pl, c, m0, nm, s);
+    if (e == hipSuccess) e = enqueue_main(pl, c, m0, nm, pl->tile, s);
+  }
+  if (e == hipSuccess) e = launch_tail(TailDev{pl->tail_entries, pl->tail_count, pl->tail_cap}, pl->d_panels, pl->d_outs, s);
+  return e;
+}
+
+extern "C" tgw_status tgw_scan(tgw_plan* pl, const uint8_t* d_geno, int64_t n_markers, int64_t row_bytes,
+                               tgw_geno_code code, int64_t m_begin, int64_t m_end, const tgw_outputs* outs,
+                               void* stream) {
+  TGW_GUARD_BEGIN
+  ScanCall c{d_geno, n_markers, row_bytes, (int)code, m_begin, m_end, outs};
+  tgw_status st = check_call(pl, c, true);
+  if (st != TGW_OK) return st;
+  if (m_begin == m_end) return TGW_OK;
+  HIP_TRY(enqueue_scan(pl, c, (hipStream_t)stream));
+  return TGW_OK;
+  TGW_GUARD_END
+}
+
+extern "C" tgw_status tgw_plan_check(tgw_plan* pl, void* stream, int64_t* n_tail) {
+  TGW_GUARD_BEGIN
+  if (!pl) return fail(TGW_ERR_INVALID_ARG, "plan is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  unsigned long long cnt = 0;
+  HIP_TRY(hipMemcpyAsync(&cnt, pl->tail_count, sizeof(cnt), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (n_tail) *n_tail = (int64_t)cnt;
+  if ((int64_t)cnt > pl->tail_cap) return fail(TGW_ERR_TAIL_OVERFLOW, "tail list overflow");
+  return TGW_OK;
+  TGW_GUARD_END
+}
+
+extern "C" tgw_status tgw_plan_autotune(tgw_plan* pl, const uint8_t* d_geno, int64_t n_markers, int64_t row_bytes,
+                                        tgw_geno_code code, int64_t m_begin, int64_t m_end,
+                                        const tgw_outputs* outs, void* stream, double* best_ms) {
+  TGW_GUARD_BEGIN
+  ScanCall c{d_geno, n_markers, row_bytes, (int)code, m_begin, m_end, outs};
+  tgw_status st = check_call(pl, c, true);
+  if (st != TGW_OK) return st;
+  if (m_begin == m_end) return fail(TGW_ERR_SHAPE, "autotune needs at least one marker");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t nm = std::min(pl->MB, m_end - m_begin);
+  HIP_TRY(enqueue_bind(pl, outs, s));
+  HIP_TRY(launch_tail_reset(TailDev{pl->tail_entries, pl->tail_count, pl->tail_cap}, s));
+  HIP_TRY(enqueue_block_stats(pl, c, m_begin, nm, s));
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  int best = pl->tile;
+  double best_t = 1e300;
+  hipError_t err = hipSuccess;
+  for (int t = 0; t < n_tile_shapes() && err == hipSuccess; ++t) {
+    err = enqueue_main(pl, c, m_begin, nm, t, s);  // warm-up
+    if (err != hipSuccess) break;
+    const int reps = 3;
+    err = hipEventRecord(e0, s);
+    for (int r = 0; r < reps && err == hipSuccess; ++r) err = enqueue_main(pl, c, m_begin, nm, t, s);
+    if (err == hipSuccess) err = hipEventRecord(e1, s);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    if (err == hipSuccess && ms / reps < best_t) {
+      best_t = ms / reps;
+      best = t;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (err != hipSuccess) return hip_fail(err, "tgw_plan_autotune");
+  pl->tile = best;
+  tune_cache_write(tune_key(pl), best);
+  if (best_ms) *best_ms = best_t;
+  return TGW_OK;
+  TGW_GUARD_END
+}
+
+extern "C" tgw_status tgw_plan_profile(tgw_plan* pl, int32_t enable) {
+  if (!pl) return fail(TGW_ERR_INVALID_ARG, "plan is NULL");
+  pl->profile = enable != 0;
+  return TGW_OK;
+}
+
+extern "C" tgw_status tgw_plan_profile_read(tgw_plan* pl, void* stream, double* main_ms, int64_t* launches) {
+  TGW_GUARD_BEGIN
+  if (!pl) return fail(TGW_ERR_INVALID_ARG, "plan is NULL");
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  double tot = 0.0;
+  hipError_t err = hipSuccess;
+  for (auto& ev : pl->prof_events) {
+    float ms = 0.f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, ev.first, ev.second);
+    tot += ms;
+    (void)hipEventDestroy(ev.first);
+    (void)hipEventDestroy(ev.second);
+  }
+  const int64_t n = (int64_t)pl->prof_events.size();
+  pl->prof_events.clear();
+  if (err != hipSuccess) return hip_fail(err, "tgw_plan_profile_read");
+  if (main_ms) *main_ms = tot;
+  if (launches) *launches = n;
+  return TGW_OK;
+  TGW_GUARD_END
+}
+
+// ---------------------------------------------------------------------------
+// graphs
+// ---------------------------------------------------------------------------
+extern "C" tgw_status tgw_graph_create(tgw_plan* pl, const uint8_t* d_geno, int64_t n_markers, int64_t row_bytes,
+                                       tgw_geno_code code, int64_t m_begin, int64_t m_end, const tgw_outputs* outs,
+                                       tgw_graph** out) {
+  TGW_GUARD_BEGIN
+  if (!out) return fail(TGW_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  ScanCall c{d_geno, n_markers, row_bytes, (int)code, m_begin, m_end, outs};
+  tgw_status st = check_call(pl, c, true);
+  if (st != TGW_OK) return st;
+  hipStream_t s;
+  HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    hipError_t e2 = m_begin < m_end ? enqueue_scan(pl, c, s) : hipSuccess;
+    e = hipStreamEndCapture(s, &g);
+    if (e2 != hipSuccess) e = e2;
+  }
+  hipGraphExec_t ex = nullptr;
+  if (e == hipSuccess) e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipStreamDestroy(s);
+  if (e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return hip_fail(e, "tgw_graph_create");
+  }
+  auto* gr = new tgw_graph();
+  gr->graph = g;
+  gr->exec = ex;
+  *out = gr;
+  return TGW_OK;
+  TGW_GUARD_END
+}
+
+extern "C" tgw_status tgw_graph_launch(tgw_graph* g, void* stream) {
+  TGW_GUARD_BEGIN
+  if (!g) return fail(TGW_ERR_INVALID_ARG, "graph is NULL");
+  HIP_TRY(hipGraphLaunch(g->exec, (hipStream_t)stream));
+  return TGW_OK;
+  TGW_GUARD_END
+}
+
+extern "C" void tgw_graph_free(tgw_graph* g) {
+  if (!g) return;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
+}
+
+// ---------------------------------------------------------------------------
+// test hooks
+// ---------------------------------------------------------------------------
+extern "C" tgw_status tgw_debug_contract(tgw_plan* pl, const uint8_t* d_geno, int64_t n_markers, int64_t row_bytes,
+                                         tgw_geno_code code, int64_t m_begin, int64_t m_end, float* d_S, int64_t lds,
+                                         void* stream) {
+  TGW_GUARD_BEGIN
+  ScanCall c{d_geno, n_markers, row_bytes, (int)code, m_begin, m_end, nullptr};
+  tgw_status st = check_call(pl, c, false);
+  if (st != TGW_OK) return st;
+  if (pl->n_panels != 1) return fail(TGW_ERR_INVALID_ARG, "debug contraction needs a one-panel plan");
+  if (!d_S) return fail(TGW_ERR_INVALID_ARG, "d_S is NULL");
+  if (lds < pl->panels[0]->P) return fail(TGW_ERR_SHAPE, "lds < n_pheno");
+  hipStream_t s = (hipStream_t)stream;
+  for (int64_t m0 = m_begin; m0 < m_end; m0 += pl->MB) {
+    const int64_t nm = std::min(pl->MB, m_end - m0);
+    StatsArgs sa{};
+    sa.geno = d_geno;
+    sa.row_bytes = row_bytes;
+    sa.m0 = m0;
+    sa.nm = nm;
+    sa.n = pl->n;
+    sa.code = (int)code;
+    sa.prec = pl->prec;
+    sa.mlut = pl->mlut;
+    sa.mstat = pl->mstat;
+    HIP_TRY(launch_stats(sa, s));
+    GemmArgs a = base_args(pl, c, m0, nm);
+    const TileShape ts = tile_shape(pl->tile);
+    a.cblocks = pl->d_cb_main;
+    a.n_cblocks = pl->n_cb;
+    a.n_ctiles = (pl->n_cb + ts.wn_frags - 1) / ts.wn_frags;
+    a.n_mtiles = (int)((nm + ts.tm() - 1) / ts.tm());
+    a.raw_out = d_S + (m0 - m_begin) * lds;
+    a.raw_ld = lds;
+    HIP_TRY(launch_gemm(pl->tile, pl->prec, kRaw, a, pl->grid_main[pl->tile], s));
+  }
+  return TGW_OK;
+  TGW_GUARD_END
+}
+
+extern "C" tgw_status tgw_debug_marker_stats(tgw_plan* pl, const uint8_t* d_geno, int64_t n_markers,
+                                             int64_t row_bytes, tgw_geno_code code, int64_t m_begin, int64_t m_end,
+                                             double* d_shift, double* d_mean, void* stream) {
+  TGW_GUARD_BEGIN
+  ScanCall c{d_geno, n_markers, row_bytes, (int)code, m_begin, m_end, nullptr};
+  tgw_status st = check_call(pl, c, false);
+  if (st != TGW_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  for (int64_t m0 = m_begin; m0 < m_end; m0 += pl->MB) {
+    const int64_t nm = std::min(pl->MB, m_end - m0);
+    StatsArgs sa{};
+    sa.geno = d_geno;
+    sa.row_bytes = row_bytes;
+    sa.m0 = m0;
+    sa.nm = nm;
+    sa.n = pl->n;
+    sa.code = (int)code;
+    sa.prec = pl->prec;
+    sa.mlut = pl->mlut;
+    sa.mstat = pl->mstat;
+    HIP_TRY(launch_stats(sa, s));
+    HIP_TRY(launch_debug_stats(pl->mstat, nm, d_shift ? d_shift + (m0 - m_begin) : nullptr,
+                               d_mean ? d_mean + (m0 - m_begin) : nullptr, s));
+  }
+  return TGW_OK;
+  TGW_GUARD_END
+}

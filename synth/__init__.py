@@ -8,6 +8,7 @@ their inputs from it without sharing any of the method.
 from .cohort import (  # noqa: F401
     CohortSpec,
     PanelSpec,
+    causal_markers,
     SEED,
     cohort_spec,
     geno_codes_np,

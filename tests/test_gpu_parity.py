@@ -1,0 +1,316 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Every input is seeded and synthetic.  Sizes span several tiles plus ragged
+tails in samples (N not a multiple of 64), markers and phenotypes.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from synth import (cohort_spec, causal_markers, geno_codes_np, pack_codes_np, packed_rows_torch, panel_inputs,
+                   row_bytes_for)
+from tests.gpu_common import R_TOL, compare, cohort_arrays, decode_codes, gpu_scan, lib, oracle_scan, say
+
+pytestmark = pytest.mark.gpu
+
+PRECS = ["split", "fp32"]
+
+
+@pytest.fixture(scope="module")
+def tgw():
+    t = lib()
+    t.init()
+    return t
+
+
+def _bf16_round(x: np.ndarray) -> np.ndarray:
+    """Round-to-nearest-even to bfloat16 (via float32), returned as float64."""
+    f = np.asarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    f = (f + 0x7FFF + ((f >> 16) & 1)) >> 16 << 16
+    return f.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+# ---------------------------------------------------------------------------
+# contraction exactness (operand layout, decode, K order, tiling, padding)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("precision", PRECS)
+@pytest.mark.parametrize("n,m,p", [(300, 70, 40), (2000, 1100, 130)])
+def test_contraction_exact_integers(tgw, precision, n, m, p):
+    say(f"case: exact contraction {precision} n={n} m={m} p={p}")
+    rng = np.random.default_rng(17 + n)
+    codes = rng.integers(0, 3, size=(m, n)).astype(np.uint8)
+    codes[5, :] = 1                      # monomorphic: shift = 1 exactly
+    V = rng.integers(-8, 9, size=(n, p)).astype(np.float32)
+    packed = pack_codes_np(codes, row_bytes_for(n))
+    cov = tgw.fit_covariates(None, n_samples=n)
+    panel = tgw.prepare_phenotypes(cov, torch.randn(n, p, dtype=torch.float32, device="cuda"), precision)
+    panel.debug_set_operand(torch.from_numpy(V).cuda())
+    plan = tgw.Plan([panel])
+    g = torch.from_numpy(packed).cuda()
+    S = plan.debug_contract(g).cpu().numpy().astype(np.float64)
+    shift, mean = [x.cpu().numpy() for x in plan.debug_marker_stats(g)]
+    np.testing.assert_array_equal(mean, codes.mean(axis=1))
+    want_shift = np.rint(64 * codes.mean(axis=1)) / 64
+    want_shift[5] = 0.0  # degenerate (monomorphic) markers are not re-centred
+    np.testing.assert_array_equal(shift, want_shift)
+    A = codes.astype(np.float64) - shift[:, None]
+    want = A @ V.astype(np.float64)
+    assert np.array_equal(want, want.astype(np.float32).astype(np.float64))  # exactly representable
+    np.testing.assert_array_equal(S, want)
+
+
+@pytest.mark.parametrize("precision", PRECS)
+def test_contraction_missing_value(tgw, precision):
+    """Missing calls enter as (mu - c) rounded to the operand type."""
+    say(f"case: contraction with missing calls {precision}")
+    rng = np.random.default_rng(5)
+    n, m, p = 777, 300, 33
+    codes = rng.integers(0, 3, size=(m, n)).astype(np.uint8)
+    codes[rng.random((m, n)) < 0.05] = 3
+    V = rng.integers(-8, 9, size=(n, p)).astype(np.float32)
+    cov = tgw.fit_covariates(None, n_samples=n)
+    panel = tgw.prepare_phenotypes(cov, torch.randn(n, p, dtype=torch.float32, device="cuda"), precision)
+    panel.debug_set_operand(torch.from_numpy(V).cuda())
+    plan = tgw.Plan([panel])
+    g = torch.from_numpy(pack_codes_np(codes, row_bytes_for(n))).cuda()
+    S = plan.debug_contract(g).cpu().numpy().astype(np.float64)
+    shift, mean = [x.cpu().numpy() for x in plan.debug_marker_stats(g)]
+    obs = codes < 3
+    mu = np.where(obs, codes, 0).sum(1) / obs.sum(1)
+    np.testing.assert_allclose(mean, mu, rtol=1e-15)
+    vm = mu - shift
+    vm_op = _bf16_round(vm) if precision == "split" else vm.astype(np.float32).astype(np.float64)
+    assert np.all(np.abs(vm - vm_op) <= (2.0 ** -16 if precision == "split" else 2.0 ** -30))
+    A = np.where(obs, codes - shift[:, None], vm_op[:, None])
+    want = A @ V.astype(np.float64)
+    scale = np.abs(A) @ np.abs(V.astype(np.float64)) + 1.0
+    assert np.max(np.abs(S - want) / scale) < 1e-6
+
+
+# ---------------------------------------------------------------------------
+# parity with the oracle
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("precision", PRECS)
+def test_cfg1_full(tgw, precision):
+    """Small workload in full: N=2,000 M=5,000 P=16 K=4, 1% missing, 20 causal markers."""
+    spec = cohort_spec("cfg1")
+    say(f"case: cfg1 full {precision}")
+    codes, packed, C, Y = cohort_arrays(spec, np.arange(spec.n_markers))
+    res, n_tail, panels = gpu_scan(C, [Y], packed, precision)
+    ref = oracle_scan(codes, C, Y)
+    compare(res[0], ref, ref["df"], f"cfg1 {precision} ")
+    # the causal markers carry real signal
+    cm = causal_markers(spec)
+    assert np.nanmax(res[0]["nlog10p"][cm]) > 10
+
+
+@pytest.mark.parametrize("precision", PRECS)
+def test_edge_cases(tgw, precision):
+    """Ragged N, K = 0, one phenotype, degenerate markers and phenotypes."""
+    rng = np.random.default_rng(23)
+    n, m = 130, 41
+    say(f"case: edge cases {precision} n={n}")
+    codes = rng.integers(0, 3, size=(m, n)).astype(np.uint8)
+    codes[rng.random((m, n)) < 0.1] = 3
+    codes[0, :] = 3                      # no observed call
+    codes[1, :] = 1                      # monomorphic
+    codes[2, :] = 2
+    codes[2, :7] = 3                     # monomorphic among observed
+    codes[3, :] = 0
+    codes[3, 5] = 1                      # a single minor allele
+    binc = (rng.random(n) < 0.5).astype(np.float64)
+    codes[4, :] = binc.astype(np.uint8)  # identical to a covariate column -> degenerate
+    C = np.column_stack([binc, rng.standard_normal(n)])
+    Y = rng.standard_normal((n, 3)).astype(np.float32)
+    Y[:, 1] = (2.0 + 3.0 * C[:, 1]).astype(np.float32)  # inside the covariate space -> degenerate
+    packed = pack_codes_np(codes, row_bytes_for(n))
+    res, _, _ = gpu_scan(C, [Y], packed, precision)
+    ref = oracle_scan(codes, C, Y)
+    assert np.all(np.isnan(res[0]["r"][[0, 1, 2, 4]]))
+    assert np.all(np.isnan(res[0]["r"][:, 1]))
+    compare(res[0], ref, ref["df"], f"edge {precision} ")
+    # K = 0, P = 1
+    res0, _, _ = gpu_scan(None, [Y[:, :1]], packed, precision)
+    ref0 = oracle_scan(codes, None, Y[:, :1])
+    assert ref0["df"] == n - 2
+    compare(res0[0], ref0, ref0["df"], f"edge K=0 {precision} ")
+
+
+@pytest.mark.parametrize("precision", PRECS)
+def test_plink_coding_and_k31(tgw, precision):
+    rng = np.random.default_rng(31)
+    n, m, k = 500, 600, 31
+    say(f"case: PLINK coding, K=31, {precision}")
+    plink_codes = rng.choice(4, size=(m, n), p=[0.4, 0.05, 0.35, 0.2]).astype(np.uint8)
+    C = rng.standard_normal((n, k))
+    Y = (rng.standard_normal((n, 37)) + C[:, :3] @ rng.standard_normal((3, 37))).astype(np.float32)
+    packed = pack_codes_np(plink_codes, row_bytes_for(n))
+    res, _, _ = gpu_scan(C, [Y], packed, precision, code=1)
+    ref = oracle_scan(plink_codes, C, Y, plink=True)
+    assert ref["df"] == n - k - 2
+    compare(res[0], ref, ref["df"], f"plink K=31 {precision} ")
+
+
+@pytest.mark.parametrize("precision", PRECS)
+def test_tail_fp64(tgw, precision):
+    """|t| > 40 goes through the FP64 tail kernel."""
+    rng = np.random.default_rng(41)
+    n, m = 3000, 64
+    say(f"case: extreme tail {precision}")
+    codes = rng.integers(0, 3, size=(m, n)).astype(np.uint8)
+    G = codes.astype(np.float64)
+    C = rng.standard_normal((n, 2))
+    Y = np.column_stack([G[0] * 3.0 + rng.standard_normal(n), G[1] * 0.6 + rng.standard_normal(n),
+                         G[2] * 10.0 + rng.standard_normal(n), rng.standard_normal(n)]).astype(np.float32)
+    packed = pack_codes_np(codes, row_bytes_for(n))
+    res, n_tail, _ = gpu_scan(C, [Y], packed, precision)
+    ref = oracle_scan(codes, C, Y)
+    assert n_tail >= 2, n_tail
+    assert ref["nlog10p"][2, 2] > 300
+    compare(res[0], ref, ref["df"], f"tail {precision} ")
+
+
+def test_errors(tgw):
+    say("case: error statuses")
+    n = 100
+    rng = np.random.default_rng(3)
+    C = rng.standard_normal((n, 3))
+    C[:, 2] = C[:, 0] - 2 * C[:, 1]
+    with pytest.raises(tgw.TgwError) as e:
+        tgw.fit_covariates(torch.from_numpy(C).cuda())
+    assert e.value.status == tgw.ERR_RANK_DEFICIENT
+    C[0, 0] = np.nan
+    with pytest.raises(tgw.TgwError) as e:
+        tgw.fit_covariates(torch.from_numpy(C).cuda())
+    assert e.value.status == tgw.ERR_NONFINITE
+    with pytest.raises(tgw.TgwError) as e:
+        tgw.fit_covariates(torch.zeros((n, 32), dtype=torch.float64, device="cuda"))
+    assert e.value.status == tgw.ERR_SHAPE
+    cov = tgw.fit_covariates(torch.from_numpy(rng.standard_normal((n, 2))).cuda())
+    Y = torch.randn(n, 4, device="cuda")
+    Y[7, 2] = float("inf")
+    with pytest.raises(tgw.TgwError) as e:
+        tgw.prepare_phenotypes(cov, Y, "split")
+    assert e.value.status == tgw.ERR_NONFINITE
+    panel = tgw.prepare_phenotypes(cov, torch.randn(n, 4, device="cuda"), "split")
+    plan = tgw.Plan([panel])
+    g = torch.zeros((10, 32), dtype=torch.uint8, device="cuda")
+    outs = tgw.make_outputs([4], 12)
+    with pytest.raises(tgw.TgwError) as e:
+        plan.scan(g, outs, 0, 11)  # m_end > n_markers
+    assert e.value.status == tgw.ERR_SHAPE
+    with pytest.raises(tgw.TgwError) as e:
+        plan.scan(torch.zeros((10, 16), dtype=torch.uint8, device="cuda"), outs)
+    assert e.value.status == tgw.ERR_SHAPE  # row too short for n = 100
+    plan.scan(g, outs, 3, 3)  # empty range is a no-op
+
+
+# ---------------------------------------------------------------------------
+# determinism, resume, graphs, batching
+# ---------------------------------------------------------------------------
+def test_determinism_resume_graph(tgw):
+    spec = cohort_spec("cfg1")
+    say("case: determinism / resume / graph replay")
+    codes, packed, C, Y = cohort_arrays(spec, np.arange(3000))
+    cov = tgw.fit_covariates(torch.from_numpy(C).cuda())
+    panel = tgw.prepare_phenotypes(cov, torch.from_numpy(Y).cuda(), "split")
+    plan = tgw.Plan([panel])
+    g = torch.from_numpy(packed).cuda()
+    a = tgw.scan(plan, g)
+    b = tgw.scan(plan, g)
+    for k in a[0]:
+        assert torch.equal(torch.nan_to_num(a[0][k], nan=7.0), torch.nan_to_num(b[0][k], nan=7.0)), k
+    # resume: two marker ranges
+    p1 = tgw.scan(plan, g, m_begin=0, m_end=1234)
+    p2 = tgw.scan(plan, g, m_begin=1234, m_end=3000)
+    for k in a[0]:
+        joined = torch.cat([p1[0][k], p2[0][k]])
+        assert torch.equal(torch.nan_to_num(joined, nan=7.0), torch.nan_to_num(a[0][k], nan=7.0)), k
+    # graph replays, with eager work in between
+    outs = tgw.make_outputs([16], 3000)
+    graph = plan.graph(g, outs)
+    for rep in range(3):
+        for o in outs[0].values():
+            o.fill_(-1.0)
+        graph.launch()
+        torch.cuda.synchronize()
+        for k in a[0]:
+            assert torch.equal(torch.nan_to_num(outs[0][k], nan=7.0), torch.nan_to_num(a[0][k], nan=7.0)), (rep, k)
+        x = torch.randn(256, 256, device="cuda")
+        (x @ x).sum().item()
+        tgw.scan(plan, g, m_begin=10, m_end=400)
+        torch.cuda.synchronize()
+
+
+def test_batching_equals_single(tgw):
+    """Several uneven panels in one plan give the same bits as one plan each."""
+    spec = cohort_spec("cfg1")
+    say("case: batching vs single panels")
+    rng = np.random.default_rng(77)
+    codes, packed, _, _ = cohort_arrays(spec, np.arange(2500))
+    n = spec.n_samples
+    sizes = [(20, 2), (70, 5), (5, 0), (33, 9)]
+    Cs, Ys = [], []
+    for p, k in sizes:
+        Cs.append(rng.standard_normal((n, k)))
+        Ys.append((rng.standard_normal((n, p))
+                   + (Cs[-1] @ rng.standard_normal((k, p)) if k else 0.0)).astype(np.float32))
+    tg = lib()
+    g = torch.from_numpy(packed).cuda()
+    covs = [tg.fit_covariates(torch.from_numpy(Cc).cuda() if Cc.shape[1] else None, n_samples=n) for Cc in Cs]
+    panels = [tg.prepare_phenotypes(cv, torch.from_numpy(Yy).cuda(), "split") for cv, Yy in zip(covs, Ys)]
+    plan_all = tg.Plan(panels)
+    outs_all = tg.scan(plan_all, g)
+    for j, pan in enumerate(panels):
+        single = tg.scan(tg.Plan([pan]), g)
+        for k in single[0]:
+            assert torch.equal(torch.nan_to_num(single[0][k], nan=7.0),
+                               torch.nan_to_num(outs_all[j][k], nan=7.0)), (j, k)
+        ref = oracle_scan(codes, Cs[j] if Cs[j].shape[1] else None, Ys[j])
+        compare({k: v.cpu().numpy() for k, v in outs_all[j].items()}, ref, ref["df"], f"batch panel {j} ")
+
+
+# ---------------------------------------------------------------------------
+# full-size workloads on sampled markers
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("precision", PRECS)
+def test_cfg2_sampled_blocks(tgw, precision):
+    """N=23,000 P=2,048 K=10: three 512-marker blocks (start, middle, end of M) + causal markers."""
+    spec = cohort_spec("cfg2")
+    M = spec.n_markers
+    markers = np.unique(np.concatenate([np.arange(0, 512), np.arange(M // 2, M // 2 + 512),
+                                        np.arange(M - 512, M), causal_markers(spec)]))
+    say(f"case: cfg2 sampled {precision} ({len(markers)} markers)")
+    codes, packed, C, Y = cohort_arrays(spec, markers)
+    res, n_tail, _ = gpu_scan(C, [Y], packed, precision)
+    ref = oracle_scan(codes, C, Y)
+    compare(res[0], ref, ref["df"], f"cfg2 {precision} ")
+
+
+def test_cfg3_bench_configuration(tgw):
+    """Precision form at full size (N=23,000, M=1,000,000, P=2,048) in the benchmark's
+    launch configuration; sampled rows are checked against the oracle."""
+    spec = cohort_spec("cfg3")
+    M, n = spec.n_markers, spec.n_samples
+    say("case: cfg3 full scan, sampled parity")
+    C, Y = panel_inputs(spec)
+    g = torch.empty((M, row_bytes_for(n)), dtype=torch.uint8, device="cuda")
+    packed_rows_torch(spec, 0, M, "cuda", out=g, chunk=8192)
+    cov = tgw.fit_covariates(torch.from_numpy(C).cuda())
+    panel = tgw.prepare_phenotypes(cov, torch.from_numpy(Y).cuda(), "split")
+    plan = tgw.Plan([panel])
+    outs = tgw.make_outputs([panel.n_pheno], M, names=("r", "nlog10p"))
+    plan.scan(g, outs)
+    plan.check()
+    rows = np.unique(np.concatenate([np.arange(0, 256), np.arange(M // 2, M // 2 + 256),
+                                     np.arange(M - 256, M), causal_markers(spec)]))
+    got = {k: v[torch.from_numpy(rows).cuda()].cpu().numpy() for k, v in outs[0].items()}
+    # the GPU-generated rows must be the generator's rows
+    assert np.array_equal(g[torch.from_numpy(rows).cuda()].cpu().numpy(),
+                          pack_codes_np(geno_codes_np(spec, rows), row_bytes_for(n)))
+    codes = geno_codes_np(spec, rows)
+    ref = oracle_scan(codes, C, Y)
+    compare(got, ref, ref["df"], "cfg3 split ")
