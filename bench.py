@@ -47,17 +47,37 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(workload: str, precision: str):
-    """HBM bytes per main-kernel launch measured with rocprofv3 counters, if the
-    kernel source has not changed since they were taken."""
-    path = os.path.join(ROOT, "profiles", f"traffic_gemm_{precision}_{workload}.json")
+def load_traffic(workload: str, precision: str, tile: int):
+    """HBM bytes per main-kernel launch measured with rocprofv3 counters
+    (profiles/traffic_gemm_<precision>_<workload>.txt, "key: value" lines), if
+    the kernel source and tile shape have not changed since they were taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_gemm_{precision}_{workload}.txt")
     if not os.path.exists(path):
         return None
+    d = {}
     with open(path) as f:
-        d = json.load(f)
-    if d.get("kernel_source_hash") != kernel_source_hash():
+        for line in f:
+            if ":" in line:
+                k, v = line.split(":", 1)
+                d[k.strip()] = v.strip()
+    if d.get("kernel_source_hash") != kernel_source_hash() or d.get("tile") != str(tile):
         return None
-    return d.get("hbm_bytes_per_launch")
+    try:
+        return float(d["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration():
+    """A plain device-to-device copy of 1 GiB (twice), for scaling the
+    FETCH_SIZE / WRITE_SIZE counters of a profiled run."""
+    import torch
+    x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(2):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": x.numel() * 4, "copies": 2}))
 
 
 def blas_threads() -> int:
@@ -100,16 +120,20 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="cfg3", choices=["cfg2", "cfg3", "cfg4"])
+    ap.add_argument("--workload", default="cfg3", choices=["cfg2", "cfg3", "cfg4", "cfg5"])
     ap.add_argument("--precision", default="split", choices=["split", "fp32"])
     ap.add_argument("--fp32-steps", type=int, default=1, help="timed steps of the FP32 scan beside (0 = skip)")
     ap.add_argument("--markers", type=int, default=0, help="override M (0 = the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-markers", type=int, default=2048)
+    ap.add_argument("--cpu-markers", type=int, default=16384)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tile", type=int, default=-1)
     ap.add_argument("--out-budget-gb", type=float, default=60.0)
+    ap.add_argument("--copy-calibration", action="store_true", help="run only the 1 GiB copy used to scale counters")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the scan shards by phenotype "
@@ -128,27 +152,35 @@ def main():
     if args.markers:
         spec = spec.__class__(**{**spec.__dict__, "n_markers": args.markers})
     N, M = spec.n_samples, spec.n_markers
-    ps = spec.panels[0]
-    P, K = ps.n_pheno, ps.n_cov
+    n_panels = len(spec.panels)
+    Ps = [p.n_pheno for p in spec.panels]
+    Ks = [p.n_cov for p in spec.panels]
+    P, K = sum(Ps), Ks[0]
 
     # ---------------------------------------------------------------- inputs
     t0 = time.perf_counter()
     geno = torch.empty((M, row_bytes_for(N)), dtype=torch.uint8, device="cuda")
     packed_rows_torch(spec, 0, M, "cuda", out=geno, chunk=8192)
-    C, Y = panel_inputs(spec)
-    Cd = torch.from_numpy(C).cuda()
-    Yd = torch.from_numpy(Y).cuda()
+    Cds, Yds = [], []
+    for j in range(n_panels):
+        C, Y = panel_inputs(spec, j)
+        Cds.append(torch.from_numpy(C).cuda())
+        Yds.append(torch.from_numpy(Y).cuda())
+        del C, Y
     torch.cuda.synchronize()
-    log(f"inputs generated in {time.perf_counter() - t0:.1f} s: N={N} M={M} P={P} K={K}")
+    log(f"inputs generated in {time.perf_counter() - t0:.1f} s: N={N} M={M} panels={n_panels} P={P} K={K}")
 
     ring = int(max(1024, min(M, args.out_budget_gb * 1e9 / (P * 20))))
-    outs = tgw.make_outputs([P], ring)
+    outs = tgw.make_outputs(Ps, ring)
     stream = torch.cuda.current_stream()
 
+    def make_plan(precision, tile):
+        covs = [tgw.fit_covariates(c) for c in Cds]
+        panels = [tgw.prepare_phenotypes(cv, y, precision) for cv, y in zip(covs, Yds)]
+        return tgw.Plan(panels, tile=tile)
+
     def one_step(precision, plan_ref, profile=False):
-        cov = tgw.fit_covariates(Cd)
-        panel = tgw.prepare_phenotypes(cov, Yd, precision)
-        plan = tgw.Plan([panel], tile=args.tile)
+        plan = make_plan(precision, args.tile)
         if profile:
             plan.profile(True)
         for m0 in range(0, M, ring):
@@ -174,9 +206,7 @@ def main():
 
     # ---------------------------------------------------------------- autotune
     if not args.no_autotune and args.tile < 0:
-        cov = tgw.fit_covariates(Cd)
-        panel = tgw.prepare_phenotypes(cov, Yd, args.precision)
-        plan = tgw.Plan([panel])
+        plan = make_plan(args.precision, -1)
         mt = min(M, ring, 131072)
         best = plan.autotune(geno, outs, 0, mt)
         log(f"autotune: tile {plan.info()['tile']} best {best:.2f} ms on {mt} markers")
@@ -211,7 +241,7 @@ def main():
         cpu = cpu_baseline(spec, min(args.cpu_markers, M))
         log(f"cpu oracle: {cpu['value']:.3e} tests/s on {cpu['cores']} threads ({cpu['seconds']:.1f} s)")
 
-    traffic = load_traffic(args.workload, args.precision)
+    traffic = load_traffic(args.workload, args.precision, info["tile"])
     line = {
         "metric": METRIC,
         "value": tests / dt,
@@ -226,9 +256,11 @@ def main():
         "dtype": "bf16" if args.precision == "split" else "fp32",
         "data": "synthetic",
         "config": {
-            "workload": f"{args.workload}: N={N} M={M} P={P} K={K}, 1% missing, 2-bit packed, "
+            "workload": f"{args.workload}: N={N} M={M} "
+                        + (f"P={P} K={K}" if n_panels == 1 else f"{n_panels} panels, sum P={P}, K {min(Ks)}-{max(Ks)}")
+                        + f", 1% missing, 2-bit packed, "
                         f"{'split BF16 hi+lo' if args.precision == 'split' else 'FP32'} contraction",
-            "n_samples": N, "n_markers": M, "n_pheno": P, "n_cov": K,
+            "n_samples": N, "n_markers": M, "n_pheno": P, "n_cov": K, "n_panels": n_panels,
             "precision": args.precision,
             "tile": {"index": info["tile"], "markers": tile_m, "cols": tile_p, "waves": waves},
             "block_markers": info["block_markers"],

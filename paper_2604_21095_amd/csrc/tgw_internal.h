@@ -47,6 +47,8 @@ struct PanelDev {
   const float2* table;  // Hermite nodes of -log10 p(|t|): (f, f' / kTabPerUnit)
   int64_t n_pheno;
   float df;
+  float sqrt_df;
+  float inv_sqrt_df;
   int32_t q;
 };
 

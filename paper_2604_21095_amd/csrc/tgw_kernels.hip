@@ -561,14 +561,91 @@ __global__ void tail_kernel(TailDev t, const PanelDev* __restrict__ panels, cons
 // are dispatched round-robin to XCDs), so that the workgroups of an XCD
 // share column tiles in their L2.
 // ---------------------------------------------------------------------------
+template <int NW>
+struct GWords {
+  typedef uint32_t type __attribute__((ext_vector_type(NW)));
+};
+template <>
+struct GWords<1> {
+  typedef uint32_t type;
+};
+// load through a global-address-space pointer (global_load_*, not flat_load_*)
+template <class T>
+__device__ __forceinline__ T gload(const void* p) {
+  static_assert(sizeof(T) % 4 == 0, "gload of whole words only");
+  typedef typename GWords<sizeof(T) / 4>::type V;
+  const V v = *(const __attribute__((address_space(1))) V*)p;
+  return __builtin_bit_cast(T, v);
+}
+template <class T>
+__device__ __forceinline__ void gstore(void* p, T v) {
+  *(__attribute__((address_space(1))) T*)p = v;
+}
+
+// -log10 p, t, beta, SE and r of one test; writes the requested outputs
+__device__ __forceinline__ void epilogue_one(float S, float invh, float invny, float sp, const PanelDev& pd,
+                                             const OutDev& od, int64_t o, int64_t row, int j, int64_t p,
+                                             const TailDev& tail) {
+  float r = S * invh * invny;
+  if (r > 1.0f) r = 1.0f;
+  if (r < -1.0f) r = -1.0f;
+  const float omr2 = (1.0f - r) * (1.0f + r);
+  const float t = r * pd.sqrt_df * rsqrtf(omr2);
+  if (od.r) gstore(od.r + o, r);
+  if (od.beta) gstore(od.beta + o, r * sp * invh);
+  if (od.se) gstore(od.se + o, sp * invh * sqrtf(omr2) * pd.inv_sqrt_df);
+  if (od.t) gstore(od.t + o, t);
+  if (od.nl) {
+    const float at = fabsf(t);
+    float nl;
+    if (at <= kTMax) {
+      nl = table_nlog10p(pd.table, at);
+    } else if (at != at) {
+      nl = at;  // NaN
+    } else {
+      nl = INFINITY;
+      if (at != INFINITY) {
+        const unsigned long long idx = atomicAdd(tail.count, 1ull);
+        if (idx < (unsigned long long)tail.capacity) {
+          TailEntry e;
+          e.row = row;
+          e.panel = j;
+          e.col = (int32_t)p;
+          e.r = r;
+          e.pad = 0.f;
+          tail.entries[idx] = e;
+        } else {
+          nl = table_nlog10p(pd.table, kTMax);  // lower bound
+        }
+      }
+    }
+    gstore(od.nl + o, nl);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// the contraction (Eq. 2) with the fused epilogue
+//
+// Workgroup tile: TM = NW * WMF * 32 markers x TP = WN * 32 columns; every
+// wave owns WMF 32-row fragments across all WN column blocks.  K loop over
+// 64-sample chunks: the column tile's operand chunk is double-buffered in
+// LDS; each wave reads its markers' packed codes straight from global memory
+// and decodes them in registers with v_perm_b32 and the per-marker table.
+// Persistent: the grid is resident and walks the (marker tile, column tile)
+// list; the list is cut into 8 contiguous ranges, one per XCD (workgroups
+// are dispatched round-robin to XCDs), so that the workgroups of an XCD
+// share column tiles in their L2.
+// ---------------------------------------------------------------------------
 template <int PREC, int NW, int WMF, int WN, int MODE>
 __global__ __launch_bounds__(NW * 64) void gemm_kernel(GemmArgs a) {
   constexpr int NT = NW * 64;
   constexpr int TM = NW * WMF * 32;
   constexpr int TILE_BYTES = WN * kBlockBytes;
-  constexpr int NV4 = TILE_BYTES / 16 / NT;
-  static_assert(TILE_BYTES % (16 * NT) == 0, "tile copy must divide evenly");
-  __shared__ __attribute__((aligned(16))) char lds[2][TILE_BYTES];
+  constexpr int RPB = kBlockBytes / 16 / NT;  // 16-byte pieces per thread per block
+  static_assert(kBlockBytes % (16 * NT) == 0, "block copy must divide evenly");
+  constexpr int STAGE_BYTES = MODE == kTest ? NW * WMF * 32 * 32 * 4 : 0;
+  constexpr int LDS_BYTES = 2 * TILE_BYTES > STAGE_BYTES ? 2 * TILE_BYTES : STAGE_BYTES;
+  __shared__ __attribute__((aligned(16))) char smem[LDS_BYTES];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -589,11 +666,13 @@ __global__ __launch_bounds__(NW * 64) void gemm_kernel(GemmArgs a) {
     const int ctile = (int)(w / a.n_mtiles);
     const int mtile = (int)(w - (int64_t)ctile * a.n_mtiles);
 
+    // operand blocks of this column tile; blocks past the end alias the
+    // first one (their columns are never written)
     const char* bop[WN];
 #pragma unroll
     for (int fn = 0; fn < WN; ++fn) {
       const int cb = ctile * WN + fn;
-      bop[fn] = cb < a.n_cblocks ? a.cblocks[cb].op : nullptr;
+      bop[fn] = a.cblocks[cb < a.n_cblocks ? cb : ctile * WN].op;
     }
     const int64_t rowbase = (int64_t)mtile * TM + wave * (WMF * 32);
     const uint8_t* ap[WMF];
@@ -603,7 +682,7 @@ __global__ __launch_bounds__(NW * 64) void gemm_kernel(GemmArgs a) {
       int64_t mr = rowbase + fm * 32 + r32;
       mr = mr < a.nm ? mr : a.nm - 1;
       ap[fm] = a.geno + (a.m0 + mr) * a.row_bytes + 8 * h;
-      lut[fm] = a.mlut[mr];
+      lut[fm] = gload<uint4>(a.mlut + mr);
     }
 
     f32x16 acc[WMF][WN];
@@ -614,27 +693,24 @@ __global__ __launch_bounds__(NW * 64) void gemm_kernel(GemmArgs a) {
 #pragma unroll
         for (int i = 0; i < 16; ++i) acc[fm][fn][i] = 0.0f;
 
-    uint4 breg[NV4];
+    u32x4 breg[WN][RPB];
     uint2 areg[WMF], anext[WMF];
     auto load_b = [&](int ch) {
 #pragma unroll
-      for (int v = 0; v < NV4; ++v) {
-        const int f = v * NT + tid;
-        const int fn = f >> 9;  // 512 uint4 per block
-        const int off = (f & 511) * 16;
-        breg[v] = bop[fn] ? *(const uint4*)(bop[fn] + (int64_t)ch * kBlockBytes + off) : make_uint4(0, 0, 0, 0);
-      }
+      for (int fn = 0; fn < WN; ++fn)
+#pragma unroll
+        for (int q = 0; q < RPB; ++q)
+          breg[fn][q] = gload<u32x4>(bop[fn] + (int64_t)ch * kBlockBytes + (q * NT + tid) * 16);
     };
     auto store_b = [&](int buf) {
 #pragma unroll
-      for (int v = 0; v < NV4; ++v) {
-        const int f = v * NT + tid;
-        *(uint4*)(&lds[buf][f * 16]) = breg[v];
-      }
+      for (int fn = 0; fn < WN; ++fn)
+#pragma unroll
+        for (int q = 0; q < RPB; ++q) *(u32x4*)(smem + buf * TILE_BYTES + fn * kBlockBytes + (q * NT + tid) * 16) = breg[fn][q];
     };
     auto load_a = [&](int ch, uint2* dst) {
 #pragma unroll
-      for (int fm = 0; fm < WMF; ++fm) dst[fm] = *(const uint2*)(ap[fm] + (int64_t)ch * 16);
+      for (int fm = 0; fm < WMF; ++fm) dst[fm] = gload<uint2>(ap[fm] + (int64_t)ch * 16);
     };
 
     load_b(0);
@@ -650,8 +726,14 @@ __global__ __launch_bounds__(NW * 64) void gemm_kernel(GemmArgs a) {
         load_b(ch + 1);
         load_a(ch + 1, anext);
       }
-      const char* tile = lds[cur];
+      const char* tile = smem + cur * TILE_BYTES;
       if constexpr (PREC == kSplit) {
+        bf16x8 bh[WN], bl[WN];
+#pragma unroll
+        for (int fn = 0; fn < WN; ++fn) {
+          bh[fn] = *(const bf16x8*)(tile + fn * kBlockBytes + (lane * 8) * 2);
+          bl[fn] = *(const bf16x8*)(tile + fn * kBlockBytes + (2048 + lane * 8) * 2);
+        }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           bf16x8 A[WMF];
@@ -668,15 +750,29 @@ __global__ __launch_bounds__(NW * 64) void gemm_kernel(GemmArgs a) {
             }
             A[fm] = __builtin_bit_cast(bf16x8, o);
           }
+          bf16x8 nh[WN], nl[WN];
+          if (j < 3) {
 #pragma unroll
-          for (int fn = 0; fn < WN; ++fn) {
-            const char* base = tile + fn * kBlockBytes;
-            const bf16x8 bh = *(const bf16x8*)(base + (j * 512 + lane * 8) * 2);
-            const bf16x8 bl = *(const bf16x8*)(base + (2048 + j * 512 + lane * 8) * 2);
+            for (int fn = 0; fn < WN; ++fn) {
+              nh[fn] = *(const bf16x8*)(tile + fn * kBlockBytes + ((j + 1) * 512 + lane * 8) * 2);
+              nl[fn] = *(const bf16x8*)(tile + fn * kBlockBytes + (2048 + (j + 1) * 512 + lane * 8) * 2);
+            }
+          }
 #pragma unroll
-            for (int fm = 0; fm < WMF; ++fm) {
-              acc[fm][fn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[fm], bh, acc[fm][fn], 0, 0, 0);
-              acc[fm][fn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[fm], bl, acc[fm][fn], 0, 0, 0);
+          for (int fn = 0; fn < WN; ++fn)
+#pragma unroll
+            for (int fm = 0; fm < WMF; ++fm)
+              acc[fm][fn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[fm], bh[fn], acc[fm][fn], 0, 0, 0);
+#pragma unroll
+          for (int fn = 0; fn < WN; ++fn)
+#pragma unroll
+            for (int fm = 0; fm < WMF; ++fm)
+              acc[fm][fn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[fm], bl[fn], acc[fm][fn], 0, 0, 0);
+          if (j < 3) {
+#pragma unroll
+            for (int fn = 0; fn < WN; ++fn) {
+              bh[fn] = nh[fn];
+              bl[fn] = nl[fn];
             }
           }
         }
@@ -730,7 +826,7 @@ __global__ __launch_bounds__(NW * 64) void gemm_kernel(GemmArgs a) {
 #pragma unroll
           for (int i = 0; i < 16; ++i) {
             const int64_t mr = rowbase + fm * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
-            if (mr < a.nm) a.raw_out[mr * a.raw_ld + blk.col0 + r32] = acc[fm][fn][i];
+            if (mr < a.nm) gstore(a.raw_out + mr * a.raw_ld + blk.col0 + r32, acc[fm][fn][i]);
           }
       }
     } else {
@@ -742,14 +838,12 @@ __global__ __launch_bounds__(NW * 64) void gemm_kernel(GemmArgs a) {
 #pragma unroll
       for (int fn = 0; fn < WN; ++fn) {
         const int cb = ctile * WN + fn;
-        if (cb >= a.n_cblocks) continue;
-        const ColBlock blk = a.cblocks[cb];
-        const PanelDev pd = a.panels[blk.panel];
-        const float* cwp = pd.cw + (int64_t)(blk.col0 + r32) * kSlots + 8 * h;
+        const ColBlock blk = a.cblocks[cb < a.n_cblocks ? cb : ctile * WN];
+        const float* cwp = a.panels[blk.panel].cw + (int64_t)(blk.col0 + r32) * kSlots + 8 * h;
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks) {
-          const float4 c0 = *(const float4*)(cwp + 16 * ks);
-          const float4 c1 = *(const float4*)(cwp + 16 * ks + 4);
+          const float4 c0 = gload<float4>(cwp + 16 * ks);
+          const float4 c1 = gload<float4>(cwp + 16 * ks + 4);
           u32x4 bo;
           bo[0] = pack_bf16x2(c0.x, c0.y);
           bo[1] = pack_bf16x2(c0.z, c0.w);
@@ -761,8 +855,8 @@ __global__ __launch_bounds__(NW * 64) void gemm_kernel(GemmArgs a) {
             int64_t mr = rowbase + fm * 32 + r32;
             mr = mr < a.nm ? mr : a.nm - 1;
             const float* wp = a.wws + (mr * a.n_panels + blk.panel) * kSlots + 16 * ks + 8 * h;
-            const float4 w0 = *(const float4*)wp;
-            const float4 w1 = *(const float4*)(wp + 4);
+            const float4 w0 = gload<float4>(wp);
+            const float4 w1 = gload<float4>(wp + 4);
             u32x4 ao;
             ao[0] = pack_bf16x2(w0.x, w0.y);
             ao[1] = pack_bf16x2(w0.z, w0.w);
@@ -773,64 +867,44 @@ __global__ __launch_bounds__(NW * 64) void gemm_kernel(GemmArgs a) {
           }
         }
       }
+      // stage one 32-column slice of the accumulators at a time through this
+      // wave's 8 KiB of LDS (the B buffers are free now), then finish the
+      // tests in a plain loop: lanes run along columns, so every output row
+      // segment is one 128-byte store per half-wave.
+      float* stage = (float*)smem + wave * (WMF * 32 * 32);
 #pragma unroll
       for (int fn = 0; fn < WN; ++fn) {
         const int cb = ctile * WN + fn;
-        if (cb >= a.n_cblocks) continue;
+        if (cb >= a.n_cblocks) break;
+#pragma unroll
+        for (int fm = 0; fm < WMF; ++fm)
+#pragma unroll
+          for (int i = 0; i < 16; ++i)
+            stage[(fm * 32 + 8 * (i >> 2) + 4 * h + (i & 3)) * 32 + r32] = acc[fm][fn][i];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         const ColBlock blk = a.cblocks[cb];
-        if (r32 >= blk.ncol) continue;
         const int j = blk.panel;
         const PanelDev pd = a.panels[j];
         const OutDev od = a.outs[j];
         const int64_t p = blk.col0 + r32;
-        const float invny = pd.invny[p];
-        const float sp = pd.scale[p];
-        const float df = pd.df;
-#pragma unroll
-        for (int fm = 0; fm < WMF; ++fm)
-#pragma unroll
-          for (int i = 0; i < 16; ++i) {
-            const int64_t mr = rowbase + fm * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
-            if (mr >= a.nm) continue;
-            const float invh = a.invh[mr * a.n_panels + j];
-            float r = acc[fm][fn][i] * invh * invny;
-            if (r > 1.0f) r = 1.0f;
-            if (r < -1.0f) r = -1.0f;
-            const float omr2 = (1.0f - r) * (1.0f + r);
-            const float t = r * sqrtf(df / omr2);
-            const int64_t o = (a.out_row0 + mr) * od.ld + p;
-            if (od.r) od.r[o] = r;
-            if (od.beta) od.beta[o] = r * sp * invh;
-            if (od.se) od.se[o] = sp * sqrtf(omr2 / df) * invh;
-            if (od.t) od.t[o] = t;
-            if (od.nl) {
-              const float at = fabsf(t);
-              float nl;
-              if (at <= kTMax) {
-                nl = table_nlog10p(pd.table, at);
-              } else if (at != at) {
-                nl = at;  // NaN
-              } else {
-                nl = INFINITY;
-                if (at != INFINITY) {
-                  const unsigned long long idx = atomicAdd(a.tail.count, 1ull);
-                  if (idx < (unsigned long long)a.tail.capacity) {
-                    TailEntry e;
-                    e.row = a.out_row0 + mr;
-                    e.panel = j;
-                    e.col = (int32_t)p;
-                    e.r = r;
-                    e.pad = 0.f;
-                    a.tail.entries[idx] = e;
-                  } else {
-                    nl = table_nlog10p(pd.table, kTMax);  // lower bound
-                  }
-                }
-              }
-              od.nl[o] = nl;
-            }
+        const bool colok = r32 < blk.ncol;
+        const float invny = colok ? gload<float>(pd.invny + p) : 0.f;
+        const float sp = colok ? gload<float>(pd.scale + p) : 0.f;
+        for (int rr = h; rr < WMF * 32; rr += 2) {
+          const int64_t mr = rowbase + rr;
+          if (colok && mr < a.nm) {
+            const float invh = gload<float>(a.invh + mr * a.n_panels + j);
+            const int64_t row = a.out_row0 + mr;
+            epilogue_one(stage[rr * 32 + r32], invh, invny, sp, pd, od, row * od.ld + p, row, j, p, a.tail);
           }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       }
+      __syncthreads();  // the next tile's prologue overwrites the staging area
     }
   }
 }

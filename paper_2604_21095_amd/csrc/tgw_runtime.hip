@@ -485,6 +485,8 @@ extern "C" tgw_status tgw_plan_create(const tgw_panel* const* panels, int32_t n_
     d.table = p->table;
     d.n_pheno = p->P;
     d.df = (float)p->df;
+    d.sqrt_df = (float)std::sqrt((double)p->df);
+    d.inv_sqrt_df = (float)(1.0 / std::sqrt((double)p->df));
     d.q = p->cov->q;
     pdv.push_back(d);
   }

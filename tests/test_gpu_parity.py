@@ -124,13 +124,15 @@ def test_edge_cases(tgw, precision):
     binc = (rng.random(n) < 0.5).astype(np.float64)
     codes[4, :] = binc.astype(np.uint8)  # identical to a covariate column -> degenerate
     C = np.column_stack([binc, rng.standard_normal(n)])
-    Y = rng.standard_normal((n, 3)).astype(np.float32)
-    Y[:, 1] = (2.0 + 3.0 * C[:, 1]).astype(np.float32)  # inside the covariate space -> degenerate
+    Y = rng.standard_normal((n, 4)).astype(np.float32)
+    Y[:, 1] = 1.0 + 3.0 * binc           # exactly inside the covariate space -> degenerate
+    Y[:, 2] = 2.5                        # constant -> degenerate
     packed = pack_codes_np(codes, row_bytes_for(n))
     res, _, _ = gpu_scan(C, [Y], packed, precision)
     ref = oracle_scan(codes, C, Y)
     assert np.all(np.isnan(res[0]["r"][[0, 1, 2, 4]]))
-    assert np.all(np.isnan(res[0]["r"][:, 1]))
+    assert np.all(np.isnan(res[0]["r"][:, 1])) and np.all(np.isnan(res[0]["r"][:, 2]))
+    assert np.all(np.isnan(ref["r"][:, 1])) and np.all(np.isnan(ref["r"][:, 2]))
     compare(res[0], ref, ref["df"], f"edge {precision} ")
     # K = 0, P = 1
     res0, _, _ = gpu_scan(None, [Y[:, :1]], packed, precision)
@@ -314,3 +316,32 @@ def test_cfg3_bench_configuration(tgw):
     codes = geno_codes_np(spec, rows)
     ref = oracle_scan(codes, C, Y)
     compare(got, ref, ref["df"], "cfg3 split ")
+
+
+def test_cfg5_batching_form_sampled(tgw):
+    """Batching form at full size: 64 panels of uneven P (log-uniform 32..4096) and
+    K (3..20) sharing N=23,000 x M=200,000 genotypes, all in one plan; sampled
+    markers of every panel are checked against the oracle."""
+    spec = cohort_spec("cfg5")
+    M, n = spec.n_markers, spec.n_samples
+    rows = np.unique(np.concatenate([np.arange(0, 24), np.arange(M // 2, M // 2 + 24),
+                                     np.arange(M - 24, M), causal_markers(spec)[:8]]))
+    say(f"case: cfg5 batching, {len(spec.panels)} panels, {len(rows)} sampled markers")
+    codes = geno_codes_np(spec, rows)
+    g = torch.from_numpy(pack_codes_np(codes, row_bytes_for(n))).cuda()
+    Cs, Ys, panels = [], [], []
+    for j in range(len(spec.panels)):
+        C, Y = panel_inputs(spec, j)
+        Cs.append(C)
+        Ys.append(Y)
+        cov = tgw.fit_covariates(torch.from_numpy(C).cuda())
+        panels.append(tgw.prepare_phenotypes(cov, torch.from_numpy(Y).cuda(), "split"))
+    plan = tgw.Plan(panels)
+    outs = tgw.scan(plan, g, names=("r", "t", "nlog10p"))
+    plan.check()
+    worst = 0.0
+    for j in range(len(spec.panels)):
+        ref = oracle_scan(codes, Cs[j], Ys[j])
+        errs = compare({k: v.cpu().numpy() for k, v in outs[j].items()}, ref, ref["df"], f"cfg5 panel {j} ")
+        worst = max(worst, errs["r"])
+    say(f"cfg5 worst |dr| over panels: {worst:.3g}")
