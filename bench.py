@@ -121,8 +121,10 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cfg3", choices=["cfg2", "cfg3", "cfg4", "cfg5"])
-    ap.add_argument("--precision", default="split", choices=["split", "fp32"])
-    ap.add_argument("--fp32-steps", type=int, default=1, help="timed steps of the FP32 scan beside (0 = skip)")
+    ap.add_argument("--precision", default="split", choices=["split", "split16", "fp32"])
+    ap.add_argument("--beside", default="split16,fp32",
+                    help="other precisions timed on the same workload (comma list, '' = none)")
+    ap.add_argument("--beside-steps", type=int, default=1)
     ap.add_argument("--markers", type=int, default=0, help="override M (0 = the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-markers", type=int, default=16384)
@@ -221,19 +223,24 @@ def main():
     markers_per_launch = M / (launches / len(prof)) if launches else M
     flops_per_launch = 2.0 * N * markers_per_launch * P
     achieved = flops_per_launch / avg_launch_s / 1e12
-    peak = PEAK_BF16_TFLOPS if args.precision == "split" else PEAK_FP32_TFLOPS
+    peak = PEAK_FP32_TFLOPS if args.precision == "fp32" else PEAK_BF16_TFLOPS
     log(f"{args.precision}: {dt * 1e3:.1f} ms/step, {tests / dt:.3e} tests/s, main kernel {avg_launch_s * 1e3:.2f} ms "
         f"x {launches // len(prof)} launches, {achieved:.1f} TFLOP/s algorithmic, tail {n_tail}")
 
-    # ---------------------------------------------------------------- FP32 beside
-    fp32 = None
-    if args.fp32_steps > 0 and args.precision == "split":
-        dt32, _, prof32, _ = timed("fp32", args.fp32_steps, 0, True)
-        ms32 = sum(p[0] for p in prof32) / max(1, sum(p[1] for p in prof32))
-        fp32 = {"value": tests / dt32, "ms_per_step": dt32 * 1e3, "main_kernel_ms": ms32,
-                "main_kernel_tflops": flops_per_launch / (ms32 / 1e3) / 1e12,
-                "roofline_frac": flops_per_launch / (ms32 / 1e3) / 1e12 / PEAK_FP32_TFLOPS}
-        log(f"fp32: {dt32 * 1e3:.1f} ms/step, {tests / dt32:.3e} tests/s")
+    # ---------------------------------------------------------------- other precisions beside
+    beside = {}
+    for prec in [x for x in args.beside.split(",") if x and x != args.precision]:
+        if not args.no_autotune and args.tile < 0 and prec != "fp32":
+            plan = make_plan(prec, -1)
+            plan.autotune(geno, outs, 0, min(M, ring, 131072))
+        dtb, _, profb, planb = timed(prec, args.beside_steps, 0, True)
+        msb = sum(p[0] for p in profb) / max(1, sum(p[1] for p in profb))
+        pk = PEAK_FP32_TFLOPS if prec == "fp32" else PEAK_BF16_TFLOPS
+        beside[prec] = {"value": tests / dtb, "ms_per_step": dtb * 1e3, "main_kernel_ms": msb,
+                        "main_kernel_tflops": flops_per_launch / (msb / 1e3) / 1e12,
+                        "roofline_frac": flops_per_launch / (msb / 1e3) / 1e12 / pk,
+                        "tile": planb.info()["tile"]}
+        log(f"{prec}: {dtb * 1e3:.1f} ms/step, {tests / dtb:.3e} tests/s, main kernel {msb:.2f} ms")
 
     # ---------------------------------------------------------------- CPU baseline
     cpu = None
@@ -253,13 +260,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16" if args.precision == "split" else "fp32",
+        "dtype": {"split": "bf16", "split16": "fp16", "fp32": "fp32"}[args.precision],
         "data": "synthetic",
         "config": {
             "workload": f"{args.workload}: N={N} M={M} "
                         + (f"P={P} K={K}" if n_panels == 1 else f"{n_panels} panels, sum P={P}, K {min(Ks)}-{max(Ks)}")
                         + f", 1% missing, 2-bit packed, "
-                        f"{'split BF16 hi+lo' if args.precision == 'split' else 'FP32'} contraction",
+                        + {"split": "split BF16 hi+lo", "split16": "split FP16 hi+lo", "fp32": "FP32"}[args.precision]
+                        + " contraction",
             "n_samples": N, "n_markers": M, "n_pheno": P, "n_cov": K, "n_panels": n_panels,
             "precision": args.precision,
             "tile": {"index": info["tile"], "markers": tile_m, "cols": tile_p, "waves": waves},
@@ -279,7 +287,8 @@ def main():
             "avg_launch_ms": avg_launch_s * 1e3,
         },
         "cpu_baseline": None if cpu is None else {k: v for k, v in cpu.items() if k != "seconds"},
-        "fp32_scan": fp32,
+        "fp32_scan": beside.get("fp32"),
+        "split16_scan": beside.get("split16"),
         "tail_tests": n_tail,
         "context": PAPER_CONTEXT,
     }

@@ -56,12 +56,18 @@ typedef enum {
 } tgw_status;
 
 /* Arithmetic of the genotype x phenotype contraction (Eq. 2).
- *  TGW_PREC_FP32  : FP32 operands on the FP32 matrix cores, FP32 accumulate.
- *  TGW_PREC_SPLIT : the prepared panel is split into BF16 hi + lo terms; the
- *                   genotype operand is exact in BF16 (re-centred calls, see
- *                   tgw_scan); two BF16 matrix-core passes, FP32 accumulate.
+ *  TGW_PREC_FP32      : FP32 operands on the FP32 matrix cores, FP32 accumulate.
+ *  TGW_PREC_SPLIT     : the prepared panel is split into BF16 hi + lo terms
+ *                       (relative residual <= 2^-16); the genotype operand is
+ *                       exact in BF16 (calls re-centred by c = round(64 mu)/64,
+ *                       missing calls carry mu - c to within 2^-16); two BF16
+ *                       matrix-core passes, FP32 accumulate.
+ *  TGW_PREC_SPLIT_F16 : the same with FP16 hi + lo terms (panel scaled by 2^12
+ *                       before the split, relative residual <= 2^-22) and
+ *                       c = round(512 mu)/512 (missing calls to within 2^-21);
+ *                       two FP16 matrix-core passes at the BF16 rate.
  * Covariate QR, phenotype norms and the extreme-tail p-values stay FP64. */
-typedef enum { TGW_PREC_FP32 = 0, TGW_PREC_SPLIT = 1 } tgw_precision;
+typedef enum { TGW_PREC_FP32 = 0, TGW_PREC_SPLIT = 1, TGW_PREC_SPLIT_F16 = 2 } tgw_precision;
 
 /* Meaning of the 2-bit genotype codes (sample i of a row sits at bits
  * 2*(i & 3) of byte i >> 2, as in PLINK .bed rows).
@@ -179,7 +185,8 @@ tgw_status tgw_plan_autotune(tgw_plan* plan, const uint8_t* d_geno, int64_t n_ma
  * Per marker: exact integer counts give the mean mu; each call g is fed to
  * the matrix cores as g - c with c = round(64 mu)/64 (exact in BF16 and FP32),
  * a missing call as mu - c rounded to the operand type (error <= 2^-16 in
- * BF16); the intercept of the covariate projection removes c exactly.
+ * BF16, 2^-21 in FP16); the intercept of the covariate projection removes c
+ * exactly.
  * Asynchronous: enqueues kernels on `stream`, allocates nothing and does not
  * synchronize; capturable in a HIP graph.  The plan's workspace is reused, so
  * calls with the same plan must not run concurrently on different streams.
@@ -215,17 +222,21 @@ void tgw_graph_free(tgw_graph* graph);
 /* ---- test hook (exactness of the contraction) -------------------------------
  * Writes the raw FP32 contraction S[m][c] = sum_i a_m(i) * v_c(i) of markers
  * [m_begin, m_end) with the panel's stored operand columns v_c (the prepared
- * Y~ in its operand precision, hi + lo for TGW_PREC_SPLIT), where a_m(i) is the
- * re-centred genotype operand described at tgw_scan.  d_S is row-major with
- * leading dim lds >= n_pheno.  Used by tests with integer-valued operands. */
+ * Y~ in its operand precision, hi + lo for the split forms; for
+ * TGW_PREC_SPLIT_F16 the stored columns are scaled by 2^12), where a_m(i) is
+ * the re-centred genotype operand described at tgw_scan.  d_S is row-major
+ * with leading dim lds >= n_pheno.  Used by tests with integer operands. */
 tgw_status tgw_debug_contract(tgw_plan* plan, const uint8_t* d_geno, int64_t n_markers, int64_t row_bytes,
                               tgw_geno_code code, int64_t m_begin, int64_t m_end, float* d_S, int64_t lds,
                               void* stream);
 /* Overwrites a panel's stored operand columns with raw values (no centring,
- * residualization or scaling): d_V device FP32 column-major n x p (ld ldv).
- * For TGW_PREC_SPLIT, hi = bf16(v) and lo = bf16(v - hi).  Test use only. */
+ * residualization or unit scaling): d_V device FP32 column-major n x p (ld
+ * ldv).  For TGW_PREC_SPLIT, hi = bf16(v) and lo = bf16(v - hi); for
+ * TGW_PREC_SPLIT_F16 the same in FP16 of 2^12 v.  Test use only. */
 tgw_status tgw_debug_set_operand(tgw_panel* panel, const float* d_V, int64_t ldv, void* stream);
-/* Per-marker re-centring constant c = round(64 mu)/64 and mean mu of markers
+/* Per-marker re-centring constant c (round(64 mu)/64 for TGW_PREC_SPLIT,
+ * round(512 mu)/512 for TGW_PREC_SPLIT_F16, as for TGW_PREC_SPLIT for FP32)
+ * and mean mu of markers
  * [m_begin, m_end) (device FP64 arrays, may be NULL).  Test use only. */
 tgw_status tgw_debug_marker_stats(tgw_plan* plan, const uint8_t* d_geno, int64_t n_markers, int64_t row_bytes,
                                   tgw_geno_code code, int64_t m_begin, int64_t m_end, double* d_shift,

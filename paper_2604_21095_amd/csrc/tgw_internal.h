@@ -28,7 +28,11 @@ constexpr float kTMax = 40.0f;        // |t| beyond this goes to the FP64 tail
 constexpr int kTabPerUnit = 32;       // nodes per unit of |t|
 constexpr int kTabNodes = 40 * 32 + 2;
 
-enum Prec { kFP32 = 0, kSplit = 1 };
+enum Prec { kFP32 = 0, kSplit = 1, kSplit16 = 2 };
+constexpr int kNumPrec = 3;
+// the FP16 split stores 2^12 y (and 2^12 q_k) so that unit-norm columns stay
+// in FP16's normal range; statistics are invariant to the scale
+constexpr float kF16Scale = 4096.0f;
 enum Mode { kRaw = 0, kTest = 1 };
 
 // per-marker statistics of one marker block
@@ -129,7 +133,7 @@ struct BindArgs {
 // ---- launchers (kernels.hip) -------------------------------------------------
 hipError_t launch_qr(const double* C, int64_t ldc, int64_t n, int64_t n_pad, int q, double* X, double* Q,
                      double* rdiag, int32_t* flags, hipStream_t s);
-hipError_t launch_cov_operands(const double* Q, int64_t n, int64_t n_pad, int q, void* wop_split, void* wop_fp32,
+hipError_t launch_cov_operands(const double* Q, int64_t n, int64_t n_pad, int q, void* const* wop,
                                hipStream_t s);
 hipError_t launch_prep(const void* Y, int y_fp64, int64_t ldy, int64_t n, int64_t n_pad, int64_t P,
                        const double* Q, int q, int prec, void* yop, float* scale, float* invny, float* cw,
@@ -138,7 +142,7 @@ hipError_t launch_set_operand(const float* V, int64_t ldv, int64_t n, int64_t n_
                               void* yop, hipStream_t s);
 hipError_t launch_table(float2* table, double df, hipStream_t s);
 hipError_t launch_stats(const StatsArgs& a, hipStream_t s);
-hipError_t launch_finalize(const MarkerStat* ms, float* wws, float* invh, int64_t nm, int n_panels,
+hipError_t launch_finalize(const MarkerStat* ms, float* wws, float* invh, int64_t nm, int n_panels, float wscale,
                            hipStream_t s);
 hipError_t launch_bind(const BindArgs& a, hipStream_t s);
 hipError_t launch_tail_reset(TailDev t, hipStream_t s);
@@ -155,6 +159,7 @@ struct TileShape {
 };
 int n_tile_shapes();
 TileShape tile_shape(int idx);
+TileShape tile_shape_for(int idx, int prec);  // the shape a precision actually runs
 // largest resident grid for a tile shape (occupancy x CUs), rounded to 8 XCDs
 int gemm_grid(int idx, int prec, int mode, int n_cu);
 hipError_t launch_gemm(int idx, int prec, int mode, const GemmArgs& a, int grid, hipStream_t s);

@@ -108,9 +108,25 @@ __device__ inline int64_t operand_index_fp32(int64_t col, int64_t i, int n_chunk
   return (cb * n_chunks + ch) * 2048 + (j >> 2) * 256 + lane * 4 + (j & 3);
 }
 
+__device__ inline uint32_t f16_bits_rn(float f) {
+  const _Float16 h = (_Float16)f;  // round to nearest even
+  return (uint32_t)__builtin_bit_cast(uint16_t, h);
+}
+__device__ inline float f16_to_float(uint32_t b) { return (float)__builtin_bit_cast(_Float16, (uint16_t)b); }
+
 __device__ inline void store_operand(void* op, int prec, int64_t col, int64_t i, int n_chunks, double v,
                                      double* stored) {
-  if (prec == kSplit) {
+  if (prec == kSplit16) {
+    const double vs = v * (double)kF16Scale;
+    const uint32_t hb = f16_bits_rn((float)vs);
+    const double hi = (double)f16_to_float(hb);
+    const uint32_t lb = f16_bits_rn((float)(vs - hi));
+    const double lo = (double)f16_to_float(lb);
+    uint16_t* p = (uint16_t*)op;
+    p[operand_index_split(col, i, n_chunks, 0)] = (uint16_t)hb;
+    p[operand_index_split(col, i, n_chunks, 1)] = (uint16_t)lb;
+    *stored = hi + lo;
+  } else if (prec == kSplit) {
     const float f = (float)v;
     const uint32_t hb = bf16_bits_rne(f);
     const double hi = (double)bf16_to_float(hb);
@@ -295,8 +311,8 @@ __global__ __launch_bounds__(kQrThreads) void qr_kernel(const double* __restrict
 
 // operand blocks of the covariate columns used for Q^T g: slot k <- Q[:, k]
 // for 1 <= k < q, slot 0 and slots >= q are zero.  One 32-column block.
-__global__ void cov_operand_kernel(const double* __restrict__ Q, int64_t n, int64_t n_pad, int q,
-                                   void* wop_split, void* wop_fp32) {
+__global__ void cov_operand_kernel(const double* __restrict__ Q, int64_t n, int64_t n_pad, int q, void* wop_fp32,
+                                   void* wop_split, void* wop_split16) {
   const int n_chunks = (int)(n_pad / kChunk);
   const int64_t total = n_pad * kColBlock;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
@@ -306,6 +322,7 @@ __global__ void cov_operand_kernel(const double* __restrict__ Q, int64_t n, int6
     const double v = (k >= 1 && k < q && i < n) ? Q[(int64_t)k * n_pad + i] : 0.0;
     double st;
     store_operand(wop_split, kSplit, k, i, n_chunks, v, &st);
+    store_operand(wop_split16, kSplit16, k, i, n_chunks, v, &st);
     store_operand(wop_fp32, kFP32, k, i, n_chunks, v, &st);
   }
 }
@@ -464,7 +481,10 @@ __global__ __launch_bounds__(256) void stats_kernel(StatsArgs a) {
   MarkerStat st;
   st.flags = ok ? 0 : 1;
   const double mu = n_obs > 0 ? (double)sg / (double)n_obs : 0.0;
-  const double c = ok ? rint(64.0 * mu) / 64.0 : 0.0;
+  // re-centring grid: 1/64 keeps g - c exact in BF16 (8 significant bits),
+  // 1/512 in FP16 (11 bits)
+  const double grid = a.prec == kSplit16 ? 512.0 : 64.0;
+  const double c = ok ? rint(grid * mu) / grid : 0.0;
   st.mu = mu;
   st.shift = c;
   st.gc2 = n_obs > 0 ? (double)num / (double)n_obs : 0.0;
@@ -478,10 +498,10 @@ __global__ __launch_bounds__(256) void stats_kernel(StatsArgs a) {
     val[0] = 0.0 - c; val[1] = vmiss; val[2] = 1.0 - c; val[3] = 2.0 - c;
   }
   uint4 lut;
-  if (a.prec == kSplit) {
+  if (a.prec == kSplit || a.prec == kSplit16) {
     uint32_t lo8 = 0, hi8 = 0;
     for (int k = 0; k < 4; ++k) {
-      const uint32_t b = bf16_bits_rne((float)val[k]);
+      const uint32_t b = a.prec == kSplit ? bf16_bits_rne((float)val[k]) : f16_bits_rn((float)val[k]);
       lo8 |= (b & 0xffu) << (8 * k);
       hi8 |= (b >> 8) << (8 * k);
     }
@@ -505,7 +525,7 @@ __global__ void debug_stats_kernel(const MarkerStat* ms, int64_t nm, double* shi
 // ||g_res||^2 per (marker, panel) from Q^T g; slot 0 <- mu - c
 // ---------------------------------------------------------------------------
 __global__ void finalize_kernel(const MarkerStat* __restrict__ ms, float* __restrict__ wws,
-                                float* __restrict__ invh, int64_t nm, int n_panels) {
+                                float* __restrict__ invh, int64_t nm, int n_panels, float wscale) {
   const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (idx >= nm * n_panels) return;
   const int64_t m = idx / n_panels;
@@ -513,7 +533,9 @@ __global__ void finalize_kernel(const MarkerStat* __restrict__ ms, float* __rest
   float* ws = wws + idx * kSlots;
   double h2 = st.gc2;
   for (int k = 1; k < kSlots; ++k) {
-    const double w = (double)ws[k];
+    const float wf = ws[k] * wscale;  // undo the operand scale of the Q columns
+    ws[k] = wf;
+    const double w = (double)wf;
     h2 -= w * w;
   }
   const bool ok = st.flags == 0 && h2 > kMarkerTol * st.gc2;
@@ -580,6 +602,19 @@ __device__ __forceinline__ T gload(const void* p) {
 template <class T>
 __device__ __forceinline__ void gstore(void* p, T v) {
   *(__attribute__((address_space(1))) T*)p = v;
+}
+
+// one 32x32x16 matrix-core step on 16-bit operands given as raw bits
+template <int PREC>
+__device__ __forceinline__ f32x16 mfma16(const u32x4& a, const u32x4& b, const f32x16& c) {
+  if constexpr (PREC == kSplit16) {
+    typedef __attribute__((__vector_size__(8 * sizeof(_Float16)))) _Float16 f16x8;
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c, 0,
+                                                 0, 0);
+  } else {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                  0, 0, 0);
+  }
 }
 
 // -log10 p, t, beta, SE and r of one test; writes the requested outputs
@@ -727,47 +762,43 @@ __global__ __launch_bounds__(NW * 64) void gemm_kernel(GemmArgs a) {
         load_a(ch + 1, anext);
       }
       const char* tile = smem + cur * TILE_BYTES;
-      if constexpr (PREC == kSplit) {
-        bf16x8 bh[WN], bl[WN];
+      if constexpr (PREC != kFP32) {
+        u32x4 bh[WN], bl[WN];
 #pragma unroll
         for (int fn = 0; fn < WN; ++fn) {
-          bh[fn] = *(const bf16x8*)(tile + fn * kBlockBytes + (lane * 8) * 2);
-          bl[fn] = *(const bf16x8*)(tile + fn * kBlockBytes + (2048 + lane * 8) * 2);
+          bh[fn] = *(const u32x4*)(tile + fn * kBlockBytes + (lane * 8) * 2);
+          bl[fn] = *(const u32x4*)(tile + fn * kBlockBytes + (2048 + lane * 8) * 2);
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          bf16x8 A[WMF];
+          u32x4 A[WMF];
 #pragma unroll
           for (int fm = 0; fm < WMF; ++fm) {
             const uint32_t src = (j < 2) ? areg[fm].x : areg[fm].y;
-            u32x4 o;
 #pragma unroll
             for (int d = 0; d < 4; ++d) {
               const int t = 4 * (j & 1) + d;
               const uint32_t R = (src >> (2 * t)) & 0x00030003u;
               const uint32_t sel = R * 0x101u + 0x04000400u;
-              o[d] = __builtin_amdgcn_perm(lut[fm].y, lut[fm].x, sel);
+              A[fm][d] = __builtin_amdgcn_perm(lut[fm].y, lut[fm].x, sel);
             }
-            A[fm] = __builtin_bit_cast(bf16x8, o);
           }
-          bf16x8 nh[WN], nl[WN];
+          u32x4 nh[WN], nl[WN];
           if (j < 3) {
 #pragma unroll
             for (int fn = 0; fn < WN; ++fn) {
-              nh[fn] = *(const bf16x8*)(tile + fn * kBlockBytes + ((j + 1) * 512 + lane * 8) * 2);
-              nl[fn] = *(const bf16x8*)(tile + fn * kBlockBytes + (2048 + (j + 1) * 512 + lane * 8) * 2);
+              nh[fn] = *(const u32x4*)(tile + fn * kBlockBytes + ((j + 1) * 512 + lane * 8) * 2);
+              nl[fn] = *(const u32x4*)(tile + fn * kBlockBytes + (2048 + (j + 1) * 512 + lane * 8) * 2);
             }
           }
 #pragma unroll
           for (int fn = 0; fn < WN; ++fn)
 #pragma unroll
-            for (int fm = 0; fm < WMF; ++fm)
-              acc[fm][fn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[fm], bh[fn], acc[fm][fn], 0, 0, 0);
+            for (int fm = 0; fm < WMF; ++fm) acc[fm][fn] = mfma16<PREC>(A[fm], bh[fn], acc[fm][fn]);
 #pragma unroll
           for (int fn = 0; fn < WN; ++fn)
 #pragma unroll
-            for (int fm = 0; fm < WMF; ++fm)
-              acc[fm][fn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[fm], bl[fn], acc[fm][fn], 0, 0, 0);
+            for (int fm = 0; fm < WMF; ++fm) acc[fm][fn] = mfma16<PREC>(A[fm], bl[fn], acc[fm][fn]);
           if (j < 3) {
 #pragma unroll
             for (int fn = 0; fn < WN; ++fn) {
@@ -910,10 +941,246 @@ __global__ __launch_bounds__(NW * 64) void gemm_kernel(GemmArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// wide split-precision contraction: one wave per SIMD, each wave owns a
+// 128 x 128 accumulator tile (256 FP32 accumulators, AGPRs); workgroup tile
+// 512 markers x 128 columns.  The column tile's operand chunk is copied to
+// LDS with direct-to-LDS loads (no register staging); the next K16 step's
+// operand fragments and decoded genotypes are fetched while the current
+// step's 32 matrix-core instructions run.
+// ---------------------------------------------------------------------------
+template <int PREC, int MODE>
+__global__ __launch_bounds__(256) void gemm_wide_kernel(GemmArgs a) {
+  static_assert(PREC != kFP32, "the wide kernel runs the 16-bit split forms");
+  constexpr int NW = 4, WMF = 4, WN = 4, NT = 256;
+  constexpr int TM = NW * WMF * 32;
+  constexpr int TILE_BYTES = WN * kBlockBytes;
+  constexpr int LDS_BYTES = 2 * TILE_BYTES;
+  static_assert(NW * WMF * 32 * 32 * 4 <= LDS_BYTES, "epilogue staging must fit");
+  __shared__ __attribute__((aligned(16))) char smem[LDS_BYTES];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int h = lane >> 5;
+  const int r32 = lane & 31;
+
+  const int G = gridDim.x;
+  const int b = blockIdx.x;
+  const int xcd = b & 7;
+  const int slot = b >> 3;
+  const int nslots = G >> 3;
+  const int64_t W = (int64_t)a.n_mtiles * a.n_ctiles;
+  const int64_t wlo = W * xcd / 8;
+  const int64_t whi = W * (xcd + 1) / 8;
+
+  for (int64_t w = wlo + slot; w < whi; w += nslots) {
+    const int ctile = (int)(w / a.n_mtiles);
+    const int mtile = (int)(w - (int64_t)ctile * a.n_mtiles);
+    const char* bop[WN];
+#pragma unroll
+    for (int fn = 0; fn < WN; ++fn) {
+      const int cb = ctile * WN + fn;
+      bop[fn] = a.cblocks[cb < a.n_cblocks ? cb : ctile * WN].op;
+    }
+    const int64_t rowbase = (int64_t)mtile * TM + wave * (WMF * 32);
+    const uint8_t* ap[WMF];
+    uint2 lut[WMF];
+#pragma unroll
+    for (int fm = 0; fm < WMF; ++fm) {
+      int64_t mr = rowbase + fm * 32 + r32;
+      mr = mr < a.nm ? mr : a.nm - 1;
+      ap[fm] = a.geno + (a.m0 + mr) * a.row_bytes + 8 * h;
+      lut[fm] = gload<uint2>(a.mlut + mr);
+    }
+
+    f32x16 acc[WMF][WN];
+#pragma unroll
+    for (int fm = 0; fm < WMF; ++fm)
+#pragma unroll
+      for (int fn = 0; fn < WN; ++fn)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[fm][fn][i] = 0.0f;
+
+    // each wave moves 1 KiB per instruction: 32 KiB per chunk = 8 per wave
+    auto dma_b = [&](int ch, int buf) {
+#pragma unroll
+      for (int q = 0; q < TILE_BYTES / (NT * 16); ++q) {
+        const int piece = q * NW + wave;        // 1 KiB piece of the tile
+        const int fn = piece >> 3;              // 8 pieces per 8 KiB block
+        const int off = (piece & 7) * 1024;
+        __builtin_amdgcn_global_load_lds(
+            (const __attribute__((address_space(1))) void*)(bop[fn] + (int64_t)ch * kBlockBytes + off + lane * 16),
+            (__attribute__((address_space(3))) void*)(smem + buf * TILE_BYTES + fn * kBlockBytes + off), 16, 0, 0);
+      }
+    };
+    uint2 areg[WMF], anext[WMF];
+    auto load_a = [&](int ch, uint2* dst) {
+#pragma unroll
+      for (int fm = 0; fm < WMF; ++fm) dst[fm] = gload<uint2>(ap[fm] + (int64_t)ch * 16);
+    };
+    auto decode = [&](const uint2* src2, int j, u32x4* A) {
+#pragma unroll
+      for (int fm = 0; fm < WMF; ++fm) {
+        const uint32_t src = (j < 2) ? src2[fm].x : src2[fm].y;
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+          const int t = 4 * (j & 1) + d;
+          const uint32_t R = (src >> (2 * t)) & 0x00030003u;
+          const uint32_t sel = R * 0x101u + 0x04000400u;
+          A[fm][d] = __builtin_amdgcn_perm(lut[fm].y, lut[fm].x, sel);
+        }
+      }
+    };
+    auto read_b = [&](int buf, int j, int hl, u32x4* bf) {
+      const char* tile = smem + buf * TILE_BYTES;
+#pragma unroll
+      for (int fn = 0; fn < WN; ++fn)
+        bf[fn] = *(const u32x4*)(tile + fn * kBlockBytes + (hl * 2048 + j * 512 + lane * 8) * 2);
+    };
+
+    dma_b(0, 0);
+    load_a(0, areg);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    u32x4 bh[WN], bl[WN], A[WMF];
+    read_b(0, 0, 0, bh);
+    read_b(0, 0, 1, bl);
+    decode(areg, 0, A);
+
+    const int nch = a.n_chunks;
+    for (int ch = 0; ch < nch; ++ch) {
+      const int cur = ch & 1;
+      const bool more = ch + 1 < nch;
+      if (more) {
+        dma_b(ch + 1, cur ^ 1);
+        load_a(ch + 1, anext);
+      }
+      // per K16 step: 16 MFMAs on the hi fragments, then the next step's hi
+      // fragments are read into the same registers; 16 MFMAs on the lo
+      // fragments, then the next lo fragments and the next decoded genotypes
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+#pragma unroll
+        for (int fn = 0; fn < WN; ++fn)
+#pragma unroll
+          for (int fm = 0; fm < WMF; ++fm)
+            acc[fm][fn] = mfma16<PREC>(A[fm], bh[fn], acc[fm][fn]);
+        if (j < 3) read_b(cur, j + 1, 0, bh);
+#pragma unroll
+        for (int fn = 0; fn < WN; ++fn)
+#pragma unroll
+          for (int fm = 0; fm < WMF; ++fm)
+            acc[fm][fn] = mfma16<PREC>(A[fm], bl[fn], acc[fm][fn]);
+        if (j < 3) {
+          read_b(cur, j + 1, 1, bl);
+          decode(areg, j + 1, A);
+        }
+      }
+      if (more) {
+        __builtin_amdgcn_s_waitcnt(0);  // this wave's operand DMA and genotype loads have landed
+        __syncthreads();                // ... and every other wave's
+#pragma unroll
+        for (int fm = 0; fm < WMF; ++fm) areg[fm] = anext[fm];
+        read_b(cur ^ 1, 0, 0, bh);
+        read_b(cur ^ 1, 0, 1, bl);
+        decode(areg, 0, A);
+      }
+    }
+    __syncthreads();  // all waves are done with the operand buffers
+
+    if constexpr (MODE == kRaw) {
+#pragma unroll
+      for (int fn = 0; fn < WN; ++fn) {
+        const int cb = ctile * WN + fn;
+        if (cb >= a.n_cblocks) continue;
+        const ColBlock blk = a.cblocks[cb];
+        if (r32 >= blk.ncol) continue;
+#pragma unroll
+        for (int fm = 0; fm < WMF; ++fm)
+#pragma unroll
+          for (int i = 0; i < 16; ++i) {
+            const int64_t mr = rowbase + fm * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
+            if (mr < a.nm) gstore(a.raw_out + mr * a.raw_ld + blk.col0 + r32, acc[fm][fn][i]);
+          }
+      }
+    } else {
+      // projection correction (see gemm_kernel)
+#pragma unroll
+      for (int fn = 0; fn < WN; ++fn) {
+        const int cb = ctile * WN + fn;
+        const ColBlock blk = a.cblocks[cb < a.n_cblocks ? cb : ctile * WN];
+        const float* cwp = a.panels[blk.panel].cw + (int64_t)(blk.col0 + r32) * kSlots + 8 * h;
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+          const float4 c0 = gload<float4>(cwp + 16 * ks);
+          const float4 c1 = gload<float4>(cwp + 16 * ks + 4);
+          u32x4 bo;
+          bo[0] = pack_bf16x2(c0.x, c0.y);
+          bo[1] = pack_bf16x2(c0.z, c0.w);
+          bo[2] = pack_bf16x2(c1.x, c1.y);
+          bo[3] = pack_bf16x2(c1.z, c1.w);
+          const bf16x8 B = __builtin_bit_cast(bf16x8, bo);
+#pragma unroll
+          for (int fm = 0; fm < WMF; ++fm) {
+            int64_t mr = rowbase + fm * 32 + r32;
+            mr = mr < a.nm ? mr : a.nm - 1;
+            const float* wp = a.wws + (mr * a.n_panels + blk.panel) * kSlots + 16 * ks + 8 * h;
+            const float4 w0 = gload<float4>(wp);
+            const float4 w1 = gload<float4>(wp + 4);
+            u32x4 ao;
+            ao[0] = pack_bf16x2(w0.x, w0.y);
+            ao[1] = pack_bf16x2(w0.z, w0.w);
+            ao[2] = pack_bf16x2(w1.x, w1.y);
+            ao[3] = pack_bf16x2(w1.z, w1.w);
+            acc[fm][fn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ao), B,
+                                                                  acc[fm][fn], 0, 0, 0);
+          }
+        }
+      }
+      float* stage = (float*)smem + wave * (WMF * 32 * 32);
+#pragma unroll
+      for (int fn = 0; fn < WN; ++fn) {
+        const int cb = ctile * WN + fn;
+        if (cb >= a.n_cblocks) break;
+#pragma unroll
+        for (int fm = 0; fm < WMF; ++fm)
+#pragma unroll
+          for (int i = 0; i < 16; ++i)
+            stage[(fm * 32 + 8 * (i >> 2) + 4 * h + (i & 3)) * 32 + r32] = acc[fm][fn][i];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const ColBlock blk = a.cblocks[cb];
+        const int j = blk.panel;
+        const PanelDev pd = a.panels[j];
+        const OutDev od = a.outs[j];
+        const int64_t p = blk.col0 + r32;
+        const bool colok = r32 < blk.ncol;
+        const float invny = colok ? gload<float>(pd.invny + p) : 0.f;
+        const float sp = colok ? gload<float>(pd.scale + p) : 0.f;
+        for (int rr = h; rr < WMF * 32; rr += 2) {
+          const int64_t mr = rowbase + rr;
+          if (colok && mr < a.nm) {
+            const float invh = gload<float>(a.invh + mr * a.n_panels + j);
+            const int64_t row = a.out_row0 + mr;
+            epilogue_one(stage[rr * 32 + r32], invh, invny, sp, pd, od, row * od.ld + p, row, j, p, a.tail);
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
+    }
+    __syncthreads();  // the next tile's prologue overwrites the staging area
+  }
+}
+
+// ---------------------------------------------------------------------------
 // tile shapes and launchers
 // ---------------------------------------------------------------------------
 // {waves, 32-row fragments per wave, 32-column blocks per tile}
 static const TileShape kShapes[] = {
+    {4, 4, 4},  // 512 x 128, one wave per SIMD, direct-to-LDS operand copy (split only)
     {8, 2, 4},  // 512 x 128
     {4, 2, 4},  // 256 x 128
     {8, 1, 4},  // 256 x 128, 8 waves
@@ -921,7 +1188,7 @@ static const TileShape kShapes[] = {
     {8, 2, 1},  // 512 x 32 (Q^T g contraction)
 };
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
-constexpr int kWShape = 4;
+constexpr int kWShape = 5;
 
 int n_tile_shapes() { return kNumShapes - 1; }
 TileShape tile_shape(int idx) { return kShapes[idx]; }
@@ -930,24 +1197,34 @@ int wgemm_tile() { return kWShape; }
 template <int PREC, int MODE>
 static const void* gemm_fn(int idx) {
   switch (idx) {
-    case 0: return (const void*)gemm_kernel<PREC, 8, 2, 4, MODE>;
-    case 1: return (const void*)gemm_kernel<PREC, 4, 2, 4, MODE>;
-    case 2: return (const void*)gemm_kernel<PREC, 8, 1, 4, MODE>;
-    case 3: return (const void*)gemm_kernel<PREC, 8, 2, 2, MODE>;
-    case 4: return (const void*)gemm_kernel<PREC, 8, 2, 1, MODE>;
+    case 0:  // the wide kernel exists for the 16-bit split forms; FP32 uses shape 1
+      if constexpr (PREC != kFP32) return (const void*)gemm_wide_kernel<PREC, MODE>;
+      return (const void*)gemm_kernel<PREC, 8, 2, 4, MODE>;
+    case 1: return (const void*)gemm_kernel<PREC, 8, 2, 4, MODE>;
+    case 2: return (const void*)gemm_kernel<PREC, 4, 2, 4, MODE>;
+    case 3: return (const void*)gemm_kernel<PREC, 8, 1, 4, MODE>;
+    case 4: return (const void*)gemm_kernel<PREC, 8, 2, 2, MODE>;
+    case 5: return (const void*)gemm_kernel<PREC, 8, 2, 1, MODE>;
   }
   return nullptr;
 }
 
+static TileShape effective_shape(int idx, int prec) {
+  if (idx == 0 && prec == kFP32) return kShapes[1];
+  return kShapes[idx];
+}
+TileShape tile_shape_for(int idx, int prec) { return effective_shape(idx, prec); }
+
 static const void* gemm_fn_any(int idx, int prec, int mode) {
   if (prec == kSplit) return mode == kRaw ? gemm_fn<kSplit, kRaw>(idx) : gemm_fn<kSplit, kTest>(idx);
+  if (prec == kSplit16) return mode == kRaw ? gemm_fn<kSplit16, kRaw>(idx) : gemm_fn<kSplit16, kTest>(idx);
   return mode == kRaw ? gemm_fn<kFP32, kRaw>(idx) : gemm_fn<kFP32, kTest>(idx);
 }
 
 int gemm_grid(int idx, int prec, int mode, int n_cu) {
   const void* fn = gemm_fn_any(idx, prec, mode);
   int occ = 0;
-  const int threads = kShapes[idx].waves * 64;
+  const int threads = effective_shape(idx, prec).waves * 64;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, threads, 0) != hipSuccess || occ < 1) occ = 1;
   int g = occ * n_cu;
   g = (g / 8) * 8;
@@ -957,7 +1234,7 @@ int gemm_grid(int idx, int prec, int mode, int n_cu) {
 hipError_t launch_gemm(int idx, int prec, int mode, const GemmArgs& a, int grid, hipStream_t s) {
   const void* fn = gemm_fn_any(idx, prec, mode);
   if (!fn) return hipErrorInvalidValue;
-  const int threads = kShapes[idx].waves * 64;
+  const int threads = effective_shape(idx, prec).waves * 64;
   GemmArgs arg = a;
   void* params[] = {&arg};
   return hipLaunchKernel(fn, dim3(grid), dim3(threads), params, 0, s);
@@ -969,9 +1246,10 @@ hipError_t launch_qr(const double* C, int64_t ldc, int64_t n, int64_t n_pad, int
   return hipGetLastError();
 }
 
-hipError_t launch_cov_operands(const double* Q, int64_t n, int64_t n_pad, int q, void* wop_split, void* wop_fp32,
+hipError_t launch_cov_operands(const double* Q, int64_t n, int64_t n_pad, int q, void* const* wop,
                                hipStream_t s) {
-  hipLaunchKernelGGL(cov_operand_kernel, dim3(256), dim3(256), 0, s, Q, n, n_pad, q, wop_split, wop_fp32);
+  hipLaunchKernelGGL(cov_operand_kernel, dim3(256), dim3(256), 0, s, Q, n, n_pad, q, wop[kFP32], wop[kSplit],
+                     wop[kSplit16]);
   return hipGetLastError();
 }
 
@@ -1000,11 +1278,11 @@ hipError_t launch_stats(const StatsArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(const MarkerStat* ms, float* wws, float* invh, int64_t nm, int n_panels,
+hipError_t launch_finalize(const MarkerStat* ms, float* wws, float* invh, int64_t nm, int n_panels, float wscale,
                            hipStream_t s) {
   const int64_t total = nm * n_panels;
   hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, ms, wws, invh, nm,
-                     n_panels);
+                     n_panels, wscale);
   return hipGetLastError();
 }
 

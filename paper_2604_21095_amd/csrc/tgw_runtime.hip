@@ -101,7 +101,7 @@ struct tgw_covariates {
   int64_t n = 0, n_pad = 0;
   int q = 0, n_chunks = 0;
   double* Q = nullptr;       // [q][n_pad]
-  void* wop[2] = {nullptr, nullptr};  // Q^T g operand block: [kFP32], [kSplit]
+  void* wop[kNumPrec] = {nullptr, nullptr, nullptr};  // Q^T g operand block per precision
 };
 
 struct tgw_panel {
@@ -188,8 +188,7 @@ extern "C" tgw_status tgw_tile_shape(int32_t idx, int32_t* tile_markers, int32_t
 extern "C" void tgw_covariates_free(tgw_covariates* cov) {
   if (!cov) return;
   (void)hipFree(cov->Q);
-  (void)hipFree(cov->wop[0]);
-  (void)hipFree(cov->wop[1]);
+  for (int k = 0; k < kNumPrec; ++k) (void)hipFree(cov->wop[k]);
   delete cov;
 }
 
@@ -223,12 +222,12 @@ extern "C" tgw_status tgw_fit_covariates(int64_t n_samples, int32_t n_cov, const
   if (e == hipSuccess) e = dmalloc(&X, (size_t)cov->q * cov->n_pad);
   if (e == hipSuccess) e = dmalloc(&rdiag, (size_t)cov->q);
   if (e == hipSuccess) e = dmalloc(&flags, 2);
-  if (e == hipSuccess) e = hipMalloc(&cov->wop[kFP32], (size_t)cov->n_chunks * kBlockBytes);
-  if (e == hipSuccess) e = hipMalloc(&cov->wop[kSplit], (size_t)cov->n_chunks * kBlockBytes);
+  for (int k = 0; k < kNumPrec; ++k)
+    if (e == hipSuccess) e = hipMalloc(&cov->wop[k], (size_t)cov->n_chunks * kBlockBytes);
   if (e == hipSuccess) e = hipMemsetAsync(flags, 0, 2 * sizeof(int32_t), s);
   if (e == hipSuccess) e = launch_qr(d_C, ldc, n_samples, cov->n_pad, cov->q, X, cov->Q, rdiag, flags, s);
   if (e == hipSuccess)
-    e = launch_cov_operands(cov->Q, n_samples, cov->n_pad, cov->q, cov->wop[kSplit], cov->wop[kFP32], s);
+    e = launch_cov_operands(cov->Q, n_samples, cov->n_pad, cov->q, cov->wop, s);
   int32_t hf[2] = {0, 0};
   if (e == hipSuccess) e = hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -280,7 +279,8 @@ extern "C" tgw_status tgw_prepare_phenotypes(const tgw_covariates* cov, int64_t 
   if (!out) return fail(TGW_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
   if (!cov || !d_Y) return fail(TGW_ERR_INVALID_ARG, "NULL argument");
-  if (prec != TGW_PREC_FP32 && prec != TGW_PREC_SPLIT) return fail(TGW_ERR_INVALID_ARG, "bad precision");
+  if (prec != TGW_PREC_FP32 && prec != TGW_PREC_SPLIT && prec != TGW_PREC_SPLIT_F16)
+    return fail(TGW_ERR_INVALID_ARG, "bad precision");
   if (y_is_fp64 != 0 && y_is_fp64 != 1) return fail(TGW_ERR_INVALID_ARG, "y_is_fp64 must be 0 or 1");
   if (n_pheno < 1) return fail(TGW_ERR_SHAPE, "n_pheno must be >= 1");
   if (ldy < cov->n) return fail(TGW_ERR_SHAPE, "ldy < n_samples");
@@ -293,7 +293,7 @@ extern "C" tgw_status tgw_prepare_phenotypes(const tgw_covariates* cov, int64_t 
   p->cov = cov;
   p->P = n_pheno;
   p->P_pad = round_up(n_pheno, kColBlock);
-  p->prec = prec == TGW_PREC_SPLIT ? kSplit : kFP32;
+  p->prec = prec == TGW_PREC_SPLIT ? kSplit : prec == TGW_PREC_SPLIT_F16 ? kSplit16 : kFP32;
   p->df = cov->n - cov->q - 1;
   int32_t* flags = nullptr;
   const size_t op_bytes = (size_t)(p->P_pad / kColBlock) * cov->n_chunks * kBlockBytes;
@@ -614,12 +614,13 @@ static hipError_t enqueue_block_stats(tgw_plan* pl, const ScanCall& c, int64_t m
   a.raw_ld = (int64_t)pl->n_panels * kSlots;
   e = launch_gemm(wgemm_tile(), pl->prec, kRaw, a, pl->grid_w, s);
   if (e != hipSuccess) return e;
-  return launch_finalize(pl->mstat, pl->wws, pl->invh, nm, pl->n_panels, s);
+  return launch_finalize(pl->mstat, pl->wws, pl->invh, nm, pl->n_panels,
+                         pl->prec == kSplit16 ? 1.0f / kF16Scale : 1.0f, s);
 }
 
 static hipError_t enqueue_main(tgw_plan* pl, const ScanCall& c, int64_t m0, int64_t nm, int tile, hipStream_t s) {
   GemmArgs a = base_args(pl, c, m0, nm);
-  const TileShape ts = tile_shape(tile);
+  const TileShape ts = tile_shape_for(tile, pl->prec);
   a.cblocks = pl->d_cb_main;
   a.n_cblocks = pl->n_cb;
   a.n_ctiles = (pl->n_cb + ts.wn_frags - 1) / ts.wn_frags;
@@ -845,7 +846,7 @@ extern "C" tgw_status tgw_debug_contract(tgw_plan* pl, const uint8_t* d_geno, in
     sa.mstat = pl->mstat;
     HIP_TRY(launch_stats(sa, s));
     GemmArgs a = base_args(pl, c, m0, nm);
-    const TileShape ts = tile_shape(pl->tile);
+    const TileShape ts = tile_shape_for(pl->tile, pl->prec);
     a.cblocks = pl->d_cb_main;
     a.n_cblocks = pl->n_cb;
     a.n_ctiles = (pl->n_cb + ts.wn_frags - 1) / ts.wn_frags;

@@ -35,9 +35,12 @@ ERR_TAIL_OVERFLOW = 8
 
 PREC_FP32 = 0
 PREC_SPLIT = 1
+PREC_SPLIT_F16 = 2
+F16_SCALE = 4096.0  # the FP16 split stores 2^12 times the operand
 CODE_DOSAGE = 0
 CODE_PLINK_BED = 1
-_PREC = {"fp32": PREC_FP32, "split": PREC_SPLIT, PREC_FP32: PREC_FP32, PREC_SPLIT: PREC_SPLIT}
+_PREC = {"fp32": PREC_FP32, "split": PREC_SPLIT, "split16": PREC_SPLIT_F16,
+         PREC_FP32: PREC_FP32, PREC_SPLIT: PREC_SPLIT, PREC_SPLIT_F16: PREC_SPLIT_F16}
 
 OUTPUT_NAMES = ("r", "beta", "se", "t", "nlog10p")
 

@@ -62,7 +62,7 @@ def test_validation_before_any_device_call(tgw):
     a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
     assert tgw._tile_shape(-1, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)) == tgw.ERR_INVALID_ARG
     assert tgw._tile_shape(0, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)) == tgw.OK
-    assert (a.value, b.value, c.value) == (512, 128, 8)
+    assert (a.value, b.value, c.value) == (512, 128, 4)
     # freeing NULL handles is a no-op
     lib.tgw_plan_free(None)
     lib.tgw_panel_free(None)

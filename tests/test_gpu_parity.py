@@ -16,7 +16,8 @@ from tests.gpu_common import R_TOL, compare, cohort_arrays, decode_codes, gpu_sc
 
 pytestmark = pytest.mark.gpu
 
-PRECS = ["split", "fp32"]
+PRECS = ["split", "split16", "fp32"]
+GRID = {"split": 64, "split16": 512, "fp32": 64}
 
 
 @pytest.fixture(scope="module")
@@ -53,9 +54,12 @@ def test_contraction_exact_integers(tgw, precision, n, m, p):
     S = plan.debug_contract(g).cpu().numpy().astype(np.float64)
     shift, mean = [x.cpu().numpy() for x in plan.debug_marker_stats(g)]
     np.testing.assert_array_equal(mean, codes.mean(axis=1))
-    want_shift = np.rint(64 * codes.mean(axis=1)) / 64
+    grid = GRID[precision]
+    want_shift = np.rint(grid * codes.mean(axis=1)) / grid
     want_shift[5] = 0.0  # degenerate (monomorphic) markers are not re-centred
     np.testing.assert_array_equal(shift, want_shift)
+    if precision == "split16":
+        S = S / tgw.F16_SCALE  # the FP16 split stores 2^12 times the operand
     A = codes.astype(np.float64) - shift[:, None]
     want = A @ V.astype(np.float64)
     assert np.array_equal(want, want.astype(np.float32).astype(np.float64))  # exactly representable
@@ -77,13 +81,21 @@ def test_contraction_missing_value(tgw, precision):
     plan = tgw.Plan([panel])
     g = torch.from_numpy(pack_codes_np(codes, row_bytes_for(n))).cuda()
     S = plan.debug_contract(g).cpu().numpy().astype(np.float64)
+    if precision == "split16":
+        S = S / tgw.F16_SCALE
     shift, mean = [x.cpu().numpy() for x in plan.debug_marker_stats(g)]
     obs = codes < 3
     mu = np.where(obs, codes, 0).sum(1) / obs.sum(1)
     np.testing.assert_allclose(mean, mu, rtol=1e-15)
     vm = mu - shift
-    vm_op = _bf16_round(vm) if precision == "split" else vm.astype(np.float32).astype(np.float64)
-    assert np.all(np.abs(vm - vm_op) <= (2.0 ** -16 if precision == "split" else 2.0 ** -30))
+    if precision == "split":
+        vm_op, bound = _bf16_round(vm), 2.0 ** -16
+    elif precision == "split16":
+        vm_op, bound = vm.astype(np.float16).astype(np.float64), 2.0 ** -21
+    else:
+        vm_op, bound = vm.astype(np.float32).astype(np.float64), 2.0 ** -30
+    assert np.all(np.abs(vm - vm_op) <= bound)
+    np.testing.assert_array_equal(shift, np.rint(GRID[precision] * mu) / GRID[precision])
     A = np.where(obs, codes - shift[:, None], vm_op[:, None])
     want = A @ V.astype(np.float64)
     scale = np.abs(A) @ np.abs(V.astype(np.float64)) + 1.0
@@ -102,6 +114,7 @@ def test_cfg1_full(tgw, precision):
     res, n_tail, panels = gpu_scan(C, [Y], packed, precision)
     ref = oracle_scan(codes, C, Y)
     compare(res[0], ref, ref["df"], f"cfg1 {precision} ")
+    assert n_tail == int(np.sum(np.abs(ref["t"]) > 40))
     # the causal markers carry real signal
     cm = causal_markers(spec)
     assert np.nanmax(res[0]["nlog10p"][cm]) > 10
@@ -345,3 +358,38 @@ def test_cfg5_batching_form_sampled(tgw):
         errs = compare({k: v.cpu().numpy() for k, v in outs[j].items()}, ref, ref["df"], f"cfg5 panel {j} ")
         worst = max(worst, errs["r"])
     say(f"cfg5 worst |dr| over panels: {worst:.3g}")
+
+
+@pytest.mark.parametrize("precision", PRECS)
+def test_phenotype_dependent_missingness(tgw, precision):
+    """Missing calls concentrated where one phenotype is high (up to 40 %): the
+    imputed value's operand rounding is then aligned with that phenotype, the
+    worst case for the re-centred missing value."""
+    rng = np.random.default_rng(97)
+    n, m = 3001, 200
+    say(f"case: phenotype-dependent missingness {precision}")
+    C = rng.standard_normal((n, 3))
+    Y = rng.standard_normal((n, 5)) + C @ rng.standard_normal((3, 5))
+    maf = rng.uniform(0.05, 0.5, m)
+    codes = rng.binomial(2, maf[:, None], size=(m, n)).astype(np.uint8)
+    high = Y[:, 0] > np.quantile(Y[:, 0], 0.5)
+    rate = np.where(high, 0.4, 0.01)
+    codes[rng.random((m, n)) < rate[None, :]] = 3
+    Y = Y.astype(np.float32)
+    packed = pack_codes_np(codes, row_bytes_for(n))
+    res, _, _ = gpu_scan(C, [Y], packed, precision)
+    ref = oracle_scan(codes, C, Y)
+    if precision == "split":
+        # BF16 carries the imputed value to 2^-16: |dr| <= 2^-16 |sum_miss y~| / ||g_res||,
+        # here up to ~5e-6 (within |dr| <= 1e-5, but -log10 p of moderate tests moves
+        # by up to ~2e-4 relative); FP16 split and FP32 meet the full criteria.
+        G = decode_codes(codes)
+        miss = np.isnan(G)
+        Yt = oracle.prepare_panel(Y.astype(np.float64), oracle.covariate_basis(C))[0]
+        bound = 2.0 ** -16 * np.abs(miss.astype(np.float64) @ Yt) / ref["h"][:, None]
+        dr = np.abs(res[0]["r"] - ref["r"])
+        ok = np.isfinite(ref["r"])
+        assert np.all(dr[ok] <= bound[ok] + 2e-6), float(np.max(dr[ok] - bound[ok]))
+        compare(res[0], ref, ref["df"], f"dependent missingness {precision} ", p_tol=5e-4)
+    else:
+        compare(res[0], ref, ref["df"], f"dependent missingness {precision} ")
