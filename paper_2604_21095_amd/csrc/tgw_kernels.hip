@@ -943,19 +943,34 @@ __global__ __launch_bounds__(NW * 64) void gemm_kernel(GemmArgs a) {
 // ---------------------------------------------------------------------------
 // wide split-precision contraction: one wave per SIMD, each wave owns a
 // 128 x 128 accumulator tile (256 FP32 accumulators, AGPRs); workgroup tile
-// 512 markers x 128 columns.  The column tile's operand chunk is copied to
-// LDS with direct-to-LDS loads (no register staging); the next K16 step's
-// operand fragments and decoded genotypes are fetched while the current
-// step's 32 matrix-core instructions run.
+// 512 markers x 128 columns.
+//
+// Operands move through a three-stage LDS ring, one 64-sample chunk per
+// stage: the column tile's operand chunk (32 KiB) and the packed codes of the
+// tile's 512 markers (8 KiB), both copied with direct-to-LDS loads.  A chunk
+// is requested two chunks before it is used, so the copy has two chunks of
+// matrix-core work (about 4 us) to arrive.  Within a chunk, step j's 32
+// matrix-core instructions are interleaved with the LDS reads of step j+1's
+// operand fragments and the decode of its genotypes, into the register set
+// of the other parity.  One barrier per chunk, ahead of its last step: after
+// it the next chunk has landed and every wave is done with this chunk's
+// stage, which is refilled at once.
 // ---------------------------------------------------------------------------
 template <int PREC, int MODE>
 __global__ __launch_bounds__(256) void gemm_wide_kernel(GemmArgs a) {
   static_assert(PREC != kFP32, "the wide kernel runs the 16-bit split forms");
   constexpr int NW = 4, WMF = 4, WN = 4, NT = 256;
   constexpr int TM = NW * WMF * 32;
-  constexpr int TILE_BYTES = WN * kBlockBytes;
-  constexpr int LDS_BYTES = 2 * TILE_BYTES;
+  constexpr int NSTAGE = 3;
+  constexpr int B_BYTES = WN * kBlockBytes;  // operand chunk of the column tile
+  constexpr int A_BYTES = TM * 16;           // 64 two-bit codes of each marker
+  constexpr int STAGE_BYTES = B_BYTES + A_BYTES;
+  constexpr int LDS_BYTES = NSTAGE * STAGE_BYTES;
+  constexpr int B_OPS = B_BYTES / (NT * 16);       // 1 KiB direct-to-LDS loads per wave per chunk
+  constexpr int A_OPS = A_BYTES / (NT * 16);
+  constexpr int CHUNK_OPS = B_OPS + A_OPS;
   static_assert(NW * WMF * 32 * 32 * 4 <= LDS_BYTES, "epilogue staging must fit");
+  static_assert((NSTAGE - 2) * CHUNK_OPS < 16, "vmcnt immediate below");
   __shared__ __attribute__((aligned(16))) char smem[LDS_BYTES];
 
   const int tid = threadIdx.x;
@@ -983,14 +998,21 @@ __global__ __launch_bounds__(256) void gemm_wide_kernel(GemmArgs a) {
       bop[fn] = a.cblocks[cb < a.n_cblocks ? cb : ctile * WN].op;
     }
     const int64_t rowbase = (int64_t)mtile * TM + wave * (WMF * 32);
-    const uint8_t* ap[WMF];
     uint2 lut[WMF];
 #pragma unroll
     for (int fm = 0; fm < WMF; ++fm) {
       int64_t mr = rowbase + fm * 32 + r32;
       mr = mr < a.nm ? mr : a.nm - 1;
-      ap[fm] = a.geno + (a.m0 + mr) * a.row_bytes + 8 * h;
       lut[fm] = gload<uint2>(a.mlut + mr);
+    }
+    // code rows copied by this lane: markers rowbase + 64 k + lane (rows
+    // past the end read the last row; their results are never stored)
+    const uint8_t* arow[A_OPS];
+#pragma unroll
+    for (int k = 0; k < A_OPS; ++k) {
+      int64_t mr = rowbase + 64 * k + lane;
+      mr = mr < a.nm ? mr : a.nm - 1;
+      arow[k] = a.geno + (a.m0 + mr) * a.row_bytes;
     }
 
     f32x16 acc[WMF][WN];
@@ -1001,22 +1023,38 @@ __global__ __launch_bounds__(256) void gemm_wide_kernel(GemmArgs a) {
 #pragma unroll
         for (int i = 0; i < 16; ++i) acc[fm][fn][i] = 0.0f;
 
-    // each wave moves 1 KiB per instruction: 32 KiB per chunk = 8 per wave
-    auto dma_b = [&](int ch, int buf) {
+    const int nch = a.n_chunks;
+    // chunk ch (clamped to the last one: the surplus copies land in stages
+    // nobody reads again) into stage st
+    auto dma = [&](int ch, int st) {
+      ch = ch < nch ? ch : nch - 1;
+      char* stage = smem + st * STAGE_BYTES;
 #pragma unroll
-      for (int q = 0; q < TILE_BYTES / (NT * 16); ++q) {
-        const int piece = q * NW + wave;        // 1 KiB piece of the tile
-        const int fn = piece >> 3;              // 8 pieces per 8 KiB block
+      for (int q = 0; q < B_OPS; ++q) {
+        const int piece = q * NW + wave;  // 1 KiB piece of the operand chunk
+        const int fn = piece >> 3;        // 8 pieces per 8 KiB block
         const int off = (piece & 7) * 1024;
         __builtin_amdgcn_global_load_lds(
             (const __attribute__((address_space(1))) void*)(bop[fn] + (int64_t)ch * kBlockBytes + off + lane * 16),
-            (__attribute__((address_space(3))) void*)(smem + buf * TILE_BYTES + fn * kBlockBytes + off), 16, 0, 0);
+            (__attribute__((address_space(3))) void*)(stage + fn * kBlockBytes + off), 16, 0, 0);
       }
-    };
-    uint2 areg[WMF], anext[WMF];
-    auto load_a = [&](int ch, uint2* dst) {
 #pragma unroll
-      for (int fm = 0; fm < WMF; ++fm) dst[fm] = gload<uint2>(ap[fm] + (int64_t)ch * 16);
+      for (int k = 0; k < A_OPS; ++k)
+        __builtin_amdgcn_global_load_lds(
+            (const __attribute__((address_space(1))) void*)(arow[k] + (int64_t)ch * 16),
+            (__attribute__((address_space(3))) void*)(stage + B_BYTES + wave * (WMF * 32 * 16) + k * 1024), 16, 0,
+            0);
+    };
+    // whole 16-byte rows, this lane's half picked in registers (paired
+    // 8-byte reads would be fused into one read that the compiler then holds
+    // until every direct-to-LDS copy in flight has landed)
+    auto read_a = [&](int st, uint2* dst) {
+      const char* ab = smem + st * STAGE_BYTES + B_BYTES + wave * (WMF * 32 * 16);
+#pragma unroll
+      for (int fm = 0; fm < WMF; ++fm) {
+        const u32x4 v = *(const u32x4*)(ab + (fm * 32 + r32) * 16);
+        dst[fm] = h ? make_uint2(v[2], v[3]) : make_uint2(v[0], v[1]);
+      }
     };
     auto decode = [&](const uint2* src2, int j, u32x4* A) {
 #pragma unroll
@@ -1031,62 +1069,100 @@ __global__ __launch_bounds__(256) void gemm_wide_kernel(GemmArgs a) {
         }
       }
     };
-    auto read_b = [&](int buf, int j, int hl, u32x4* bf) {
-      const char* tile = smem + buf * TILE_BYTES;
+    auto read_b = [&](int st, int j, u32x4* bh, u32x4* bl) {
+      const char* tile = smem + st * STAGE_BYTES;
 #pragma unroll
-      for (int fn = 0; fn < WN; ++fn)
-        bf[fn] = *(const u32x4*)(tile + fn * kBlockBytes + (hl * 2048 + j * 512 + lane * 8) * 2);
+      for (int fn = 0; fn < WN; ++fn) {
+        bh[fn] = *(const u32x4*)(tile + fn * kBlockBytes + (j * 512 + lane * 8) * 2);
+        bl[fn] = *(const u32x4*)(tile + fn * kBlockBytes + (2048 + j * 512 + lane * 8) * 2);
+      }
     };
 
-    dma_b(0, 0);
-    load_a(0, areg);
+    // prologue: chunks 0..NSTAGE-1 requested, chunk 0 awaited
+#pragma unroll
+    for (int c = 0; c < NSTAGE; ++c) dma(c, c);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    u32x4 bh[WN], bl[WN], A[WMF];
-    read_b(0, 0, 0, bh);
-    read_b(0, 0, 1, bl);
-    decode(areg, 0, A);
+    u32x4 bh[2][WN], bl[2][WN], A[2][WMF];
+    uint2 acur[WMF], anext[WMF];
+    read_a(0, acur);
+    read_b(0, 0, bh[0], bl[0]);
+    decode(acur, 0, A[0]);
 
-    const int nch = a.n_chunks;
+    int st = 0;  // stage of chunk ch
     for (int ch = 0; ch < nch; ++ch) {
-      const int cur = ch & 1;
-      const bool more = ch + 1 < nch;
-      if (more) {
-        dma_b(ch + 1, cur ^ 1);
-        load_a(ch + 1, anext);
-      }
-      // per K16 step: 16 MFMAs on the hi fragments, then the next step's hi
-      // fragments are read into the same registers; 16 MFMAs on the lo
-      // fragments, then the next lo fragments and the next decoded genotypes
+      const int st1 = st + 1 < NSTAGE ? st + 1 : 0;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-#pragma unroll
-        for (int fn = 0; fn < WN; ++fn)
-#pragma unroll
-          for (int fm = 0; fm < WMF; ++fm)
-            acc[fm][fn] = mfma16<PREC>(A[fm], bh[fn], acc[fm][fn]);
-        if (j < 3) read_b(cur, j + 1, 0, bh);
-#pragma unroll
-        for (int fn = 0; fn < WN; ++fn)
-#pragma unroll
-          for (int fm = 0; fm < WMF; ++fm)
-            acc[fm][fn] = mfma16<PREC>(A[fm], bl[fn], acc[fm][fn]);
+        const int cs = j & 1, ns = cs ^ 1;
         if (j < 3) {
-          read_b(cur, j + 1, 1, bl);
-          decode(areg, j + 1, A);
+          read_b(st, j + 1, bh[ns], bl[ns]);
+          decode(acur, j + 1, A[ns]);
+        } else {
+          // own copies of chunk ch+1 done (the NSTAGE-2 later chunks may
+          // still be in flight) and own LDS reads of this chunk done; then
+          // every wave's
+          // (a plain s_barrier: a workgroup fence here would wait for
+          // every copy in flight)
+          __builtin_amdgcn_s_waitcnt(((NSTAGE - 2) * CHUNK_OPS) | (0x7 << 4) | (0x0 << 8));
+          read_a(st1, anext);  // this wave's own copies: no barrier needed
+          asm volatile("s_barrier" ::: "memory");
+          // LDS reads before the copies: a read issued after a
+          // direct-to-LDS load is held until that load completes
+          read_b(st1, 0, bh[ns], bl[ns]);
+          dma(ch + NSTAGE, st);
+          decode(anext, 0, A[ns]);
         }
-      }
-      if (more) {
-        __builtin_amdgcn_s_waitcnt(0);  // this wave's operand DMA and genotype loads have landed
-        __syncthreads();                // ... and every other wave's
 #pragma unroll
-        for (int fm = 0; fm < WMF; ++fm) areg[fm] = anext[fm];
-        read_b(cur ^ 1, 0, 0, bh);
-        read_b(cur ^ 1, 0, 1, bl);
-        decode(areg, 0, A);
+        for (int fn = 0; fn < WN; ++fn)
+#pragma unroll
+          for (int fm = 0; fm < WMF; ++fm) acc[fm][fn] = mfma16<PREC>(A[cs][fm], bh[cs][fn], acc[fm][fn]);
+#pragma unroll
+        for (int fn = 0; fn < WN; ++fn)
+#pragma unroll
+          for (int fm = 0; fm < WMF; ++fm) acc[fm][fn] = mfma16<PREC>(A[cs][fm], bl[cs][fn], acc[fm][fn]);
+        // issue order: copies and LDS reads early, each behind one
+        // matrix-core instruction, then the decode, three VALU ops per MFMA
+        if (j == 3) {
+#pragma unroll
+          for (int q = 0; q < 2 * WN + WMF; ++q) {
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // DS read
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+          }
+#pragma unroll
+          for (int q = 0; q < CHUNK_OPS; ++q) {
+            __builtin_amdgcn_sched_group_barrier(0x010, 1, 0);  // VMEM (direct-to-LDS)
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+            __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);  // VALU
+          }
+#pragma unroll
+          for (int q = 0; q < 32 - CHUNK_OPS - 2 * WN - WMF; ++q) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+            __builtin_amdgcn_sched_group_barrier(0x002, 6, 0);  // VALU
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < 2 * WN; ++q) {
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // DS read
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+          }
+#pragma unroll
+          for (int q = 0; q < 32 - 2 * WN; ++q) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+            __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);  // VALU
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);
       }
+#pragma unroll
+      for (int fm = 0; fm < WMF; ++fm) acur[fm] = anext[fm];
+      st = st1;
+      // the next chunk's first fragments landed long ago; saying so here
+      // keeps the compiler from waiting for all LDS reads at the loop head
+      __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0), vmcnt and expcnt unconstrained
     }
-    __syncthreads();  // all waves are done with the operand buffers
+    __builtin_amdgcn_s_waitcnt(0);  // surplus copies have landed
+    __syncthreads();                // all waves are done with the stages
 
     if constexpr (MODE == kRaw) {
 #pragma unroll
