@@ -121,7 +121,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cfg3", choices=["cfg2", "cfg3", "cfg4", "cfg5"])
-    ap.add_argument("--precision", default="split", choices=["split", "split16", "fp32"])
+    ap.add_argument("--precision", default="split", choices=["split", "split16", "split8", "fp32"])
     ap.add_argument("--beside", default="split16,fp32",
                     help="other precisions timed on the same workload (comma list, '' = none)")
     ap.add_argument("--beside-steps", type=int, default=1)
@@ -260,13 +260,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"split": "bf16", "split16": "fp16", "fp32": "fp32"}[args.precision],
+        "dtype": {"split": "bf16", "split16": "fp16", "split8": "fp16+fp8", "fp32": "fp32"}[args.precision],
         "data": "synthetic",
         "config": {
             "workload": f"{args.workload}: N={N} M={M} "
                         + (f"P={P} K={K}" if n_panels == 1 else f"{n_panels} panels, sum P={P}, K {min(Ks)}-{max(Ks)}")
                         + f", 1% missing, 2-bit packed, "
-                        + {"split": "split BF16 hi+lo", "split16": "split FP16 hi+lo", "fp32": "FP32"}[args.precision]
+                        + {"split": "split BF16 hi+lo", "split16": "split FP16 hi+lo",
+                           "split8": "FP16 hi + FP8 e4m3 lo", "fp32": "FP32"}[args.precision]
                         + " contraction",
             "n_samples": N, "n_markers": M, "n_pheno": P, "n_cov": K, "n_panels": n_panels,
             "precision": args.precision,
@@ -288,7 +289,9 @@ def main():
         },
         "cpu_baseline": None if cpu is None else {k: v for k, v in cpu.items() if k != "seconds"},
         "fp32_scan": beside.get("fp32"),
+        "split_scan": beside.get("split"),
         "split16_scan": beside.get("split16"),
+        "split8_scan": beside.get("split8"),
         "tail_tests": n_tail,
         "context": PAPER_CONTEXT,
     }

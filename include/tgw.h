@@ -55,7 +55,10 @@ typedef enum {
   TGW_ERR_TAIL_OVERFLOW = 8   /* more extreme-tail tests than the plan's list holds */
 } tgw_status;
 
-/* Arithmetic of the genotype x phenotype contraction (Eq. 2).
+/* Arithmetic of the genotype x phenotype contraction (Eq. 2).  The scan's
+ * statistics are computed from what the operands actually hold (the column
+ * norms and covariate projections of the stored, rounded panel), so the
+ * rounding of the panel perturbs r by about its relative residual / sqrt(3).
  *  TGW_PREC_FP32      : FP32 operands on the FP32 matrix cores, FP32 accumulate.
  *  TGW_PREC_SPLIT     : the prepared panel is split into BF16 hi + lo terms
  *                       (relative residual <= 2^-16); the genotype operand is
@@ -66,8 +69,22 @@ typedef enum {
  *                       before the split, relative residual <= 2^-22) and
  *                       c = round(512 mu)/512 (missing calls to within 2^-21);
  *                       two FP16 matrix-core passes at the BF16 rate.
+ *  TGW_PREC_SPLIT_F8  : FP16 hi term of 2^12 y~ against the FP16 genotype
+ *                       operand of TGW_PREC_SPLIT_F16, plus the lo term
+ *                       2^12 y~ - hi in FP8 e4m3 (OCP), scaled per column by
+ *                       a power of two (E8M0 block scale of the matrix core)
+ *                       against the genotype operand rounded to e4m3:
+ *                       relative residual of the panel <= about 2^-16, one
+ *                       FP16 pass plus one FP8 pass at twice the FP16 rate.
+ *                       Runs on the wide tile shape only (every tile index
+ *                       selects it).
  * Covariate QR, phenotype norms and the extreme-tail p-values stay FP64. */
-typedef enum { TGW_PREC_FP32 = 0, TGW_PREC_SPLIT = 1, TGW_PREC_SPLIT_F16 = 2 } tgw_precision;
+typedef enum {
+  TGW_PREC_FP32 = 0,
+  TGW_PREC_SPLIT = 1,
+  TGW_PREC_SPLIT_F16 = 2,
+  TGW_PREC_SPLIT_F8 = 3
+} tgw_precision;
 
 /* Meaning of the 2-bit genotype codes (sample i of a row sits at bits
  * 2*(i & 3) of byte i >> 2, as in PLINK .bed rows).
@@ -136,7 +153,7 @@ tgw_status tgw_covariates_q(const tgw_covariates* cov, double* d_Q, int64_t ldq,
 /* ---- phenotype panel (paper Methods 2.2, Eq. 1 + standardization) -------
  * Once per panel: Y_c = Y - mean(Y); Y_res = (I - Q Q^T) Y_c;
  * s_p = ||Y_res,p|| (FP64); Y~ = Y_res / s_p; then Y~ is stored in the
- * scan's operand layout (FP32, or BF16 hi + lo for TGW_PREC_SPLIT) together
+ * scan's operand layout (FP32, or the hi + lo terms of the split forms) together
  * with per-column FP64-derived constants and the p-value table for
  * df = n_samples - q - 1.
  *   d_Y   device, column-major n_samples x n_pheno, FP32 (y_is_fp64 = 0) or
@@ -223,7 +240,8 @@ void tgw_graph_free(tgw_graph* graph);
  * Writes the raw FP32 contraction S[m][c] = sum_i a_m(i) * v_c(i) of markers
  * [m_begin, m_end) with the panel's stored operand columns v_c (the prepared
  * Y~ in its operand precision, hi + lo for the split forms; for
- * TGW_PREC_SPLIT_F16 the stored columns are scaled by 2^12), where a_m(i) is
+ * TGW_PREC_SPLIT_F16 and TGW_PREC_SPLIT_F8 the stored columns are scaled by
+ * 2^12), where a_m(i) is
  * the re-centred genotype operand described at tgw_scan.  d_S is row-major
  * with leading dim lds >= n_pheno.  Used by tests with integer operands. */
 tgw_status tgw_debug_contract(tgw_plan* plan, const uint8_t* d_geno, int64_t n_markers, int64_t row_bytes,
@@ -232,10 +250,13 @@ tgw_status tgw_debug_contract(tgw_plan* plan, const uint8_t* d_geno, int64_t n_m
 /* Overwrites a panel's stored operand columns with raw values (no centring,
  * residualization or unit scaling): d_V device FP32 column-major n x p (ld
  * ldv).  For TGW_PREC_SPLIT, hi = bf16(v) and lo = bf16(v - hi); for
- * TGW_PREC_SPLIT_F16 the same in FP16 of 2^12 v.  Test use only. */
+ * TGW_PREC_SPLIT_F16 the same in FP16 of 2^12 v; for TGW_PREC_SPLIT_F8,
+ * hi = fp16(2^12 v) and lo = e4m3 of (2^12 v - hi) with the column's scale.
+ * Test use only. */
 tgw_status tgw_debug_set_operand(tgw_panel* panel, const float* d_V, int64_t ldv, void* stream);
 /* Per-marker re-centring constant c (round(64 mu)/64 for TGW_PREC_SPLIT,
- * round(512 mu)/512 for TGW_PREC_SPLIT_F16, as for TGW_PREC_SPLIT for FP32)
+ * round(512 mu)/512 for TGW_PREC_SPLIT_F16 and TGW_PREC_SPLIT_F8, as for
+ * TGW_PREC_SPLIT for FP32)
  * and mean mu of markers
  * [m_begin, m_end) (device FP64 arrays, may be NULL).  Test use only. */
 tgw_status tgw_debug_marker_stats(tgw_plan* plan, const uint8_t* d_geno, int64_t n_markers, int64_t row_bytes,

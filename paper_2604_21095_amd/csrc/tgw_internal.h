@@ -9,12 +9,14 @@ namespace tgw {
 // ---- operand layout -------------------------------------------------------
 // Samples are processed in chunks of 64 (the contraction's K chunk).  A
 // prepared panel (and the covariate columns used for Q^T g) is stored as
-// column blocks of 32 columns; block (cb, ch) = 8 KiB holding columns
-// 32cb..32cb+31 for samples 64ch..64ch+63, arranged exactly as the matrix
-// core reads them (see kernels: operand_index_split / operand_index_fp32).
+// column blocks of 32 columns; block (cb, ch) holds columns 32cb..32cb+31
+// for samples 64ch..64ch+63, arranged exactly as the matrix core reads them
+// (see kernels: operand_index_split / operand_index_fp32 / operand_index_lo8):
+// 8 KiB for FP32 and the 16-bit splits, 6 KiB for FP16 hi + FP8 lo.
 constexpr int kChunk = 64;
 constexpr int kColBlock = 32;
 constexpr int kBlockBytes = 8192;
+constexpr int kBlockBytes8 = 6144;
 constexpr int kSlots = 32;      // correction slots per (marker, panel): dmu, Q^T g
 constexpr int kMaxCov = 31;     // K <= 31 so that q = K + 1 <= 32 slots
 constexpr int kMaxPanelsPerBind = 32;
@@ -28,17 +30,24 @@ constexpr float kTMax = 40.0f;        // |t| beyond this goes to the FP64 tail
 constexpr int kTabPerUnit = 32;       // nodes per unit of |t|
 constexpr int kTabNodes = 40 * 32 + 2;
 
-enum Prec { kFP32 = 0, kSplit = 1, kSplit16 = 2 };
-constexpr int kNumPrec = 3;
-// the FP16 split stores 2^12 y (and 2^12 q_k) so that unit-norm columns stay
+// kSplit8: FP16 hi term of 2^12 y against FP16 genotypes, plus the FP8 e4m3
+// lo term (scaled per column by a power of two) against FP8 genotypes
+enum Prec { kFP32 = 0, kSplit = 1, kSplit16 = 2, kSplit8 = 3 };
+constexpr int kNumPrec = 4;
+// the FP16 forms store 2^12 y (and 2^12 q_k) so that unit-norm columns stay
 // in FP16's normal range; statistics are invariant to the scale
 constexpr float kF16Scale = 4096.0f;
+__host__ __device__ constexpr int block_bytes(int prec) { return prec == kSplit8 ? kBlockBytes8 : kBlockBytes; }
+// precision of the Q^T g contraction (the FP8 form has no covariate operand
+// of its own: Q^T g runs on the FP16 split)
+__host__ __device__ constexpr int wprec(int prec) { return prec == kSplit8 ? kSplit16 : prec; }
+__host__ __device__ constexpr bool f16_scaled(int prec) { return prec == kSplit16 || prec == kSplit8; }
 enum Mode { kRaw = 0, kTest = 1 };
 
 // per-marker statistics of one marker block
 struct MarkerStat {
   double gc2;    // ||g_c||^2 of the mean-imputed marker (exact from integer counts)
-  float dmu;     // mu - c, c = round(64 mu) / 64 (the re-centring constant)
+  float dmu;     // mu - c, c = mu rounded to 1/64 (BF16) or 1/512 (FP16 forms)
   int32_t flags; // 1 = degenerate (no observed call or monomorphic)
   double mu;
   double shift;  // c
@@ -49,6 +58,7 @@ struct PanelDev {
   const float* invny;   // 1 / ||(I - QQ^T) y_op,p||  (NaN for degenerate columns)
   const float* cw;      // [P_pad][32]: (-sum_i y_op, -q_k^T y_op for k >= 1, 0 ...)
   const float2* table;  // Hermite nodes of -log10 p(|t|): (f, f' / kTabPerUnit)
+  const uint8_t* lscale; // FP8 form: E8M0 scale of each column's lo term (NULL otherwise)
   int64_t n_pheno;
   float df;
   float sqrt_df;
@@ -67,7 +77,7 @@ struct OutDev {
 
 // one 32-column block of the virtual concatenation of all panels' columns
 struct ColBlock {
-  const char* op;  // operand base of this block: chunk ch at op + ch * kBlockBytes
+  const char* op;  // operand base of this block: chunk ch at op + ch * block_bytes(prec)
   int32_t panel;   // owning panel
   int32_t col0;    // local column of the block's first column (RAW: output column)
   int32_t ncol;    // valid columns in this block
@@ -103,7 +113,7 @@ struct GemmArgs {
   const ColBlock* cblocks;
   const PanelDev* panels;
   const OutDev* outs;
-  const uint4* mlut;     // [nm] decode table of each marker
+  const uint4* mlut;     // [nm] decode table of each marker (16-bit: x lo bytes, y hi bytes; z FP8 bytes)
   const float* wws;      // [nm][n_panels][32]
   const float* invh;     // [nm][n_panels]
   float* raw_out;        // RAW mode destination
@@ -137,9 +147,9 @@ hipError_t launch_cov_operands(const double* Q, int64_t n, int64_t n_pad, int q,
                                hipStream_t s);
 hipError_t launch_prep(const void* Y, int y_fp64, int64_t ldy, int64_t n, int64_t n_pad, int64_t P,
                        const double* Q, int q, int prec, void* yop, float* scale, float* invny, float* cw,
-                       int32_t* flags, hipStream_t s);
+                       uint8_t* lscale, int32_t* flags, hipStream_t s);
 hipError_t launch_set_operand(const float* V, int64_t ldv, int64_t n, int64_t n_pad, int64_t P, int prec,
-                              void* yop, hipStream_t s);
+                              void* yop, uint8_t* lscale, hipStream_t s);
 hipError_t launch_table(float2* table, double df, hipStream_t s);
 hipError_t launch_stats(const StatsArgs& a, hipStream_t s);
 hipError_t launch_finalize(const MarkerStat* ms, float* wws, float* invh, int64_t nm, int n_panels, float wscale,
@@ -162,6 +172,7 @@ TileShape tile_shape(int idx);
 TileShape tile_shape_for(int idx, int prec);  // the shape a precision actually runs
 // largest resident grid for a tile shape (occupancy x CUs), rounded to 8 XCDs
 int gemm_grid(int idx, int prec, int mode, int n_cu);
+int tile_alias(int idx, int prec);  // smallest tile index that runs the same kernel
 hipError_t launch_gemm(int idx, int prec, int mode, const GemmArgs& a, int grid, hipStream_t s);
 int wgemm_tile();  // tile shape used for the Q^T g contraction
 

@@ -37,6 +37,19 @@ __device__ inline uint32_t pack_bf16x2(float lo, float hi) {
 }
 
 template <int NT>
+__device__ inline double block_max(double v, double* sh) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double m = 0.0;
+#pragma unroll
+  for (int i = 0; i < NT / 64; ++i) m = fmax(m, sh[i]);
+  return m;
+}
+
+template <int NT>
 __device__ inline double block_sum(double v, double* sh) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -80,7 +93,10 @@ __device__ inline void block_sum_vec(double* v, double* sh) {
 // FP32: block (cb, ch) holds 2048 floats: [j >> 2][lane][j & 3], j = K2 step,
 // sample 64 ch + 32 h + j.
 // ---------------------------------------------------------------------------
-__device__ inline int64_t operand_index_split(int64_t col, int64_t i, int n_chunks, int hl) {
+// stride: 16-bit elements per block (4096 for the 16-bit splits; 3072 for
+// FP16 hi + FP8 lo, whose block keeps only the hi half in this layout)
+__device__ inline int64_t operand_index_split(int64_t col, int64_t i, int n_chunks, int hl,
+                                              int64_t stride = 4096) {
   const int64_t cb = col >> 5;
   const int c = (int)(col & 31);
   const int64_t ch = i >> 6;
@@ -94,7 +110,7 @@ __device__ inline int64_t operand_index_split(int64_t col, int64_t i, int n_chun
   const int j = 2 * jhi + jlo;
   const int e = 2 * d + b;
   const int lane = 32 * h + c;
-  return (cb * n_chunks + ch) * 4096 + hl * 2048 + j * 512 + lane * 8 + e;
+  return (cb * n_chunks + ch) * stride + hl * 2048 + j * 512 + lane * 8 + e;
 }
 
 __device__ inline int64_t operand_index_fp32(int64_t col, int64_t i, int n_chunks) {
@@ -108,15 +124,73 @@ __device__ inline int64_t operand_index_fp32(int64_t col, int64_t i, int n_chunk
   return (cb * n_chunks + ch) * 2048 + (j >> 2) * 256 + lane * 4 + (j & 3);
 }
 
+// FP16 hi + FP8 lo: block (cb, ch) = 6 KiB.  Bytes [0, 4096) hold the FP16
+// hi terms in the split layout's hi half; bytes [4096, 6144) the e4m3 lo
+// terms as [part][lane][16 bytes].  A lane (32 h + column) holds 32 bytes,
+// dword D = 4 part + t, byte k; it feeds sample 64 ch + 32 h + 16 part +
+// 4 k + t, the order in which the genotype FP8 decode emits them.
+__device__ inline int64_t operand_index_lo8(int64_t col, int64_t i, int n_chunks) {
+  const int64_t cb = col >> 5;
+  const int c = (int)(col & 31);
+  const int64_t ch = i >> 6;
+  const int s = (int)(i & 63);
+  const int h = s >> 5;
+  const int part = (s >> 4) & 1;
+  const int k = (s >> 2) & 3;
+  const int t = s & 3;
+  const int lane = 32 * h + c;
+  return (cb * n_chunks + ch) * kBlockBytes8 + 4096 + part * 1024 + lane * 16 + 4 * t + k;
+}
+
 __device__ inline uint32_t f16_bits_rn(float f) {
   const _Float16 h = (_Float16)f;  // round to nearest even
   return (uint32_t)__builtin_bit_cast(uint16_t, h);
 }
 __device__ inline float f16_to_float(uint32_t b) { return (float)__builtin_bit_cast(_Float16, (uint16_t)b); }
 
+// OCP FP8 E4M3 (bias 7, no infinities, largest finite 448, subnormals
+// m * 2^-9), round to nearest even.  |x| must not exceed 448.
+__device__ inline uint32_t e4m3_bits_rne(double x) {
+  const uint32_t sign = x < 0.0 ? 0x80u : 0u;
+  const double a = fabs(x);
+  if (a < 0x1p-6) {
+    const double m = rint(a * 0x1p9);  // subnormal step 2^-9; m = 8 is the smallest normal
+    return sign | (uint32_t)m;
+  }
+  int e = ilogb(a);
+  double q = rint(ldexp(a, 3 - e)) - 8.0;  // 3 fraction bits
+  if (q >= 8.0) {
+    q = 0.0;
+    ++e;
+  }
+  return sign | (uint32_t)((e + 7) << 3) | (uint32_t)q;
+}
+__device__ inline double e4m3_value(uint32_t b) {
+  const int e = (b >> 3) & 15, m = b & 7;
+  const double v = e == 0 ? ldexp((double)m, -9) : ldexp(1.0 + m / 8.0, e - 7);
+  return (b & 0x80u) ? -v : v;
+}
+
+// power-of-two shift that brings a column's largest FP8 lo term near the top
+// of the e4m3 range (0 for a column without lo terms)
+__device__ inline int lo_shift(double maxlo) {
+  if (!(maxlo > 0.0)) return 0;
+  int s = ilogb(448.0 / maxlo);
+  return s < -100 ? -100 : (s > 100 ? 100 : s);
+}
+
+// lsh: the column's FP8 lo shift (FP16 hi + FP8 lo form only)
 __device__ inline void store_operand(void* op, int prec, int64_t col, int64_t i, int n_chunks, double v,
-                                     double* stored) {
-  if (prec == kSplit16) {
+                                     double* stored, int lsh = 0) {
+  if (prec == kSplit8) {
+    const double vs = v * (double)kF16Scale;
+    const uint32_t hb = f16_bits_rn((float)vs);
+    const double hi = (double)f16_to_float(hb);
+    const uint32_t qb = e4m3_bits_rne(ldexp(vs - hi, lsh));
+    ((uint16_t*)op)[operand_index_split(col, i, n_chunks, 0, kBlockBytes8 / 2)] = (uint16_t)hb;
+    ((uint8_t*)op)[operand_index_lo8(col, i, n_chunks)] = (uint8_t)qb;
+    *stored = hi + ldexp(e4m3_value(qb), -lsh);
+  } else if (prec == kSplit16) {
     const double vs = v * (double)kF16Scale;
     const uint32_t hb = f16_bits_rn((float)vs);
     const double hi = (double)f16_to_float(hb);
@@ -336,7 +410,7 @@ __global__ __launch_bounds__(kPrepThreads) void prep_kernel(const void* __restri
                                                             int64_t n, int64_t n_pad, int64_t P,
                                                             const double* __restrict__ Q, int q, int prec,
                                                             void* yop, float* scale, float* invny, float* cw,
-                                                            int32_t* flags) {
+                                                            uint8_t* lscale, int32_t* flags) {
   __shared__ double sh[(kPrepThreads / 64) * (kSlots + 2)];
   __shared__ double qty_s[kSlots];
   const int64_t p = blockIdx.x;
@@ -389,6 +463,21 @@ __global__ __launch_bounds__(kPrepThreads) void prep_kernel(const void* __restri
   const bool valid = sp > 1e-12 * sqrt(yc2);
   const double inv = valid ? 1.0 / sp : 0.0;
 
+  // pass 3b (FP8 lo form): the column's largest lo term sets its scale
+  int lsh = 0;
+  if (prec == kSplit8) {
+    double mx = 0.0;
+    for (int64_t i = tid; i < n; i += kPrepThreads) {
+      double v = yval(i) - mean;
+      for (int k = 0; k < q; ++k) v -= Q[(int64_t)k * n_pad + i] * qty_s[k];
+      const double vs = v * inv * (double)kF16Scale;
+      mx = fmax(mx, fabs(vs - (double)f16_to_float(f16_bits_rn((float)vs))));
+    }
+    mx = block_max<kPrepThreads>(mx, sh);
+    lsh = lo_shift(mx);
+    if (tid == 0) lscale[p] = (uint8_t)(127 - lsh);
+  }
+
   // pass 4: y~ = y_res / s_p into the operand; accumulate what the stored
   // (rounded) operand actually holds: sum, norm^2 and Q^T y_op
 #pragma unroll
@@ -397,7 +486,7 @@ __global__ __launch_bounds__(kPrepThreads) void prep_kernel(const void* __restri
     double v = yval(i) - mean;
     for (int k = 0; k < q; ++k) v -= Q[(int64_t)k * n_pad + i] * qty_s[k];
     double st;
-    store_operand(yop, prec, p, i, n_chunks, v * inv, &st);
+    store_operand(yop, prec, p, i, n_chunks, v * inv, &st, lsh);
     acc[kSlots] += st;
     acc[kSlots + 1] += st * st;
 #pragma unroll
@@ -423,8 +512,21 @@ __global__ __launch_bounds__(kPrepThreads) void prep_kernel(const void* __restri
 }
 
 // test hook: raw operand columns (no centring / scaling)
+__global__ __launch_bounds__(kPrepThreads) void set_lscale_kernel(const float* __restrict__ V, int64_t ldv,
+                                                                  int64_t n, uint8_t* lscale) {
+  __shared__ double sh[kPrepThreads / 64];
+  const int64_t p = blockIdx.x;
+  double mx = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += kPrepThreads) {
+    const double vs = (double)V[p * ldv + i] * (double)kF16Scale;
+    mx = fmax(mx, fabs(vs - (double)f16_to_float(f16_bits_rn((float)vs))));
+  }
+  mx = block_max<kPrepThreads>(mx, sh);
+  if (threadIdx.x == 0) lscale[p] = (uint8_t)(127 - lo_shift(mx));
+}
+
 __global__ void set_operand_kernel(const float* __restrict__ V, int64_t ldv, int64_t n, int64_t n_pad,
-                                   int64_t P, int prec, void* yop) {
+                                   int64_t P, int prec, void* yop, const uint8_t* lscale) {
   const int n_chunks = (int)(n_pad / kChunk);
   const int64_t total = n_pad * P;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
@@ -433,7 +535,7 @@ __global__ void set_operand_kernel(const float* __restrict__ V, int64_t ldv, int
     const int64_t i = idx % n_pad;
     const double v = i < n ? (double)V[p * ldv + i] : 0.0;
     double st;
-    store_operand(yop, prec, p, i, n_chunks, v, &st);
+    store_operand(yop, prec, p, i, n_chunks, v, &st, prec == kSplit8 ? 127 - (int)lscale[p] : 0);
   }
 }
 
@@ -483,7 +585,7 @@ __global__ __launch_bounds__(256) void stats_kernel(StatsArgs a) {
   const double mu = n_obs > 0 ? (double)sg / (double)n_obs : 0.0;
   // re-centring grid: 1/64 keeps g - c exact in BF16 (8 significant bits),
   // 1/512 in FP16 (11 bits)
-  const double grid = a.prec == kSplit16 ? 512.0 : 64.0;
+  const double grid = f16_scaled(a.prec) ? 512.0 : 64.0;
   const double c = ok ? rint(grid * mu) / grid : 0.0;
   st.mu = mu;
   st.shift = c;
@@ -498,14 +600,15 @@ __global__ __launch_bounds__(256) void stats_kernel(StatsArgs a) {
     val[0] = 0.0 - c; val[1] = vmiss; val[2] = 1.0 - c; val[3] = 2.0 - c;
   }
   uint4 lut;
-  if (a.prec == kSplit || a.prec == kSplit16) {
-    uint32_t lo8 = 0, hi8 = 0;
+  if (a.prec != kFP32) {
+    uint32_t lo8 = 0, hi8 = 0, f8 = 0;
     for (int k = 0; k < 4; ++k) {
       const uint32_t b = a.prec == kSplit ? bf16_bits_rne((float)val[k]) : f16_bits_rn((float)val[k]);
       lo8 |= (b & 0xffu) << (8 * k);
       hi8 |= (b >> 8) << (8 * k);
+      f8 |= e4m3_bits_rne(val[k]) << (8 * k);  // the FP8 lo pass sees g - c rounded to e4m3
     }
-    lut = make_uint4(lo8, hi8, 0u, 0u);
+    lut = make_uint4(lo8, hi8, f8, 0u);
   } else {
     lut = make_uint4(__float_as_uint((float)val[0]), __float_as_uint((float)val[1]),
                      __float_as_uint((float)val[2]), __float_as_uint((float)val[3]));
@@ -607,7 +710,7 @@ __device__ __forceinline__ void gstore(void* p, T v) {
 // one 32x32x16 matrix-core step on 16-bit operands given as raw bits
 template <int PREC>
 __device__ __forceinline__ f32x16 mfma16(const u32x4& a, const u32x4& b, const f32x16& c) {
-  if constexpr (PREC == kSplit16) {
+  if constexpr (f16_scaled(PREC)) {
     typedef __attribute__((__vector_size__(8 * sizeof(_Float16)))) _Float16 f16x8;
     return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c, 0,
                                                  0, 0);
@@ -945,32 +1048,47 @@ __global__ __launch_bounds__(NW * 64) void gemm_kernel(GemmArgs a) {
 // 128 x 128 accumulator tile (256 FP32 accumulators, AGPRs); workgroup tile
 // 512 markers x 128 columns.
 //
-// Operands move through a three-stage LDS ring, one 64-sample chunk per
-// stage: the column tile's operand chunk (32 KiB) and the packed codes of the
-// tile's 512 markers (8 KiB), both copied with direct-to-LDS loads.  A chunk
-// is requested two chunks before it is used, so the copy has two chunks of
-// matrix-core work (about 4 us) to arrive.  Within a chunk, step j's 32
-// matrix-core instructions are interleaved with the LDS reads of step j+1's
-// operand fragments and the decode of its genotypes, into the register set
-// of the other parity.  One barrier per chunk, ahead of its last step: after
-// it the next chunk has landed and every wave is done with this chunk's
-// stage, which is refilled at once.
+// Operands move through an LDS ring, one 64-sample chunk per stage: the
+// column tile's operand chunk and the packed codes of the tile's 512 markers
+// (8 KiB), both copied with direct-to-LDS loads.  A chunk is requested
+// NSTAGE - 1 chunks before it is used.  Within a chunk, step j's matrix-core
+// instructions are interleaved with the LDS reads of step j+1's operand
+// fragments and the decode of its genotypes, into the register set of the
+// other parity.  One barrier per chunk, ahead of its last step: after it the
+// next chunk has landed and every wave is done with this chunk's stage,
+// which is refilled at once.
+//
+// Forms: the 16-bit splits run 32 MFMA 32x32x16 per step (hi and lo terms);
+// FP16 hi + FP8 lo runs 16 FP16 MFMA per step plus, for the step's marker
+// fragment fm = j, 4 block-scaled FP8 MFMA 32x32x64 over the whole chunk
+// (E8M0 scale of each column's lo term on the B side).
 // ---------------------------------------------------------------------------
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+
+// s_waitcnt immediate: vmcnt(vm), lgkmcnt(0), expcnt unconstrained
+constexpr int waitcnt_vm_lgkm0(int vm) { return (vm & 15) | ((vm >> 4) << 14) | (0x7 << 4); }
+
 template <int PREC, int MODE>
 __global__ __launch_bounds__(256) void gemm_wide_kernel(GemmArgs a) {
-  static_assert(PREC != kFP32, "the wide kernel runs the 16-bit split forms");
+  static_assert(PREC != kFP32, "the wide kernel runs the split forms");
+  constexpr bool F8 = PREC == kSplit8;
   constexpr int NW = 4, WMF = 4, WN = 4, NT = 256;
   constexpr int TM = NW * WMF * 32;
-  constexpr int NSTAGE = 3;
-  constexpr int B_BYTES = WN * kBlockBytes;  // operand chunk of the column tile
-  constexpr int A_BYTES = TM * 16;           // 64 two-bit codes of each marker
+  constexpr int BB = block_bytes(PREC);
+  constexpr int NSTAGE = F8 ? 4 : 3;
+  constexpr int B_BYTES = WN * BB;  // operand chunk of the column tile
+  constexpr int A_BYTES = TM * 16;  // 64 two-bit codes of each marker
   constexpr int STAGE_BYTES = B_BYTES + A_BYTES;
   constexpr int LDS_BYTES = NSTAGE * STAGE_BYTES;
-  constexpr int B_OPS = B_BYTES / (NT * 16);       // 1 KiB direct-to-LDS loads per wave per chunk
+  constexpr int PPB = BB / 1024;                // 1 KiB pieces per operand block
+  constexpr int B_OPS = B_BYTES / (NT * 16);    // direct-to-LDS loads per wave per chunk
   constexpr int A_OPS = A_BYTES / (NT * 16);
   constexpr int CHUNK_OPS = B_OPS + A_OPS;
+  constexpr int HI_MFMA = F8 ? WMF * WN : 2 * WMF * WN;  // 16-bit MFMA per step
+  constexpr int MFMA_STEP = HI_MFMA + (F8 ? WN : 0);
+  constexpr int DS_STEP = F8 ? WN : 2 * WN;              // fragment reads per step
   static_assert(NW * WMF * 32 * 32 * 4 <= LDS_BYTES, "epilogue staging must fit");
-  static_assert((NSTAGE - 2) * CHUNK_OPS < 16, "vmcnt immediate below");
+  static_assert((NSTAGE - 2) * CHUNK_OPS < 64, "vmcnt range");
   __shared__ __attribute__((aligned(16))) char smem[LDS_BYTES];
 
   const int tid = threadIdx.x;
@@ -992,18 +1110,32 @@ __global__ __launch_bounds__(256) void gemm_wide_kernel(GemmArgs a) {
     const int ctile = (int)(w / a.n_mtiles);
     const int mtile = (int)(w - (int64_t)ctile * a.n_mtiles);
     const char* bop[WN];
+    int bscale[WN];  // FP8 form: E8M0 scale of this lane's column, per block
 #pragma unroll
     for (int fn = 0; fn < WN; ++fn) {
       const int cb = ctile * WN + fn;
-      bop[fn] = a.cblocks[cb < a.n_cblocks ? cb : ctile * WN].op;
+      const ColBlock blk = a.cblocks[cb < a.n_cblocks ? cb : ctile * WN];
+      bop[fn] = blk.op;
+      bscale[fn] = 127;
+      if constexpr (F8) {
+        if (cb < a.n_cblocks && r32 < blk.ncol) bscale[fn] = a.panels[blk.panel].lscale[blk.col0 + r32];
+      }
     }
     const int64_t rowbase = (int64_t)mtile * TM + wave * (WMF * 32);
     uint2 lut[WMF];
+    uint32_t lut8[WMF];
 #pragma unroll
     for (int fm = 0; fm < WMF; ++fm) {
       int64_t mr = rowbase + fm * 32 + r32;
       mr = mr < a.nm ? mr : a.nm - 1;
-      lut[fm] = gload<uint2>(a.mlut + mr);
+      if constexpr (F8) {
+        const uint4 l4 = gload<uint4>(a.mlut + mr);
+        lut[fm] = make_uint2(l4.x, l4.y);
+        lut8[fm] = l4.z;
+      } else {
+        lut[fm] = gload<uint2>(a.mlut + mr);
+        lut8[fm] = 0u;
+      }
     }
     // code rows copied by this lane: markers rowbase + 64 k + lane (rows
     // past the end read the last row; their results are never stored)
@@ -1032,11 +1164,11 @@ __global__ __launch_bounds__(256) void gemm_wide_kernel(GemmArgs a) {
 #pragma unroll
       for (int q = 0; q < B_OPS; ++q) {
         const int piece = q * NW + wave;  // 1 KiB piece of the operand chunk
-        const int fn = piece >> 3;        // 8 pieces per 8 KiB block
-        const int off = (piece & 7) * 1024;
+        const int fn = piece / PPB;
+        const int off = (piece % PPB) * 1024;
         __builtin_amdgcn_global_load_lds(
-            (const __attribute__((address_space(1))) void*)(bop[fn] + (int64_t)ch * kBlockBytes + off + lane * 16),
-            (__attribute__((address_space(3))) void*)(stage + fn * kBlockBytes + off), 16, 0, 0);
+            (const __attribute__((address_space(1))) void*)(bop[fn] + (int64_t)ch * BB + off + lane * 16),
+            (__attribute__((address_space(3))) void*)(stage + fn * BB + off), 16, 0, 0);
       }
 #pragma unroll
       for (int k = 0; k < A_OPS; ++k)
@@ -1056,6 +1188,7 @@ __global__ __launch_bounds__(256) void gemm_wide_kernel(GemmArgs a) {
         dst[fm] = h ? make_uint2(v[2], v[3]) : make_uint2(v[0], v[1]);
       }
     };
+    // 16-bit values of K16 step j: two per dword via the per-marker table
     auto decode = [&](const uint2* src2, int j, u32x4* A) {
 #pragma unroll
       for (int fm = 0; fm < WMF; ++fm) {
@@ -1069,12 +1202,35 @@ __global__ __launch_bounds__(256) void gemm_wide_kernel(GemmArgs a) {
         }
       }
     };
+    // e4m3 values of fragment fm over the whole chunk: four per dword
+    auto decode8 = [&](const uint2* src2, int fm, i32x8& A8) {
+#pragma unroll
+      for (int part = 0; part < 2; ++part) {
+        const uint32_t src = part ? src2[fm].y : src2[fm].x;
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          A8[4 * part + t] = (int)__builtin_amdgcn_perm(lut8[fm], lut8[fm], (src >> (2 * t)) & 0x03030303u);
+      }
+    };
     auto read_b = [&](int st, int j, u32x4* bh, u32x4* bl) {
       const char* tile = smem + st * STAGE_BYTES;
 #pragma unroll
       for (int fn = 0; fn < WN; ++fn) {
-        bh[fn] = *(const u32x4*)(tile + fn * kBlockBytes + (j * 512 + lane * 8) * 2);
-        bl[fn] = *(const u32x4*)(tile + fn * kBlockBytes + (2048 + j * 512 + lane * 8) * 2);
+        bh[fn] = *(const u32x4*)(tile + fn * BB + (j * 512 + lane * 8) * 2);
+        if constexpr (!F8) bl[fn] = *(const u32x4*)(tile + fn * BB + (2048 + j * 512 + lane * 8) * 2);
+      }
+    };
+    auto read_b8 = [&](int st, i32x8* B8) {
+      const char* tile = smem + st * STAGE_BYTES;
+#pragma unroll
+      for (int fn = 0; fn < WN; ++fn) {
+        const u32x4 p0 = *(const u32x4*)(tile + fn * BB + 4096 + lane * 16);
+        const u32x4 p1 = *(const u32x4*)(tile + fn * BB + 4096 + 1024 + lane * 16);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          B8[fn][t] = (int)p0[t];
+          B8[fn][4 + t] = (int)p1[t];
+        }
       }
     };
 
@@ -1084,10 +1240,12 @@ __global__ __launch_bounds__(256) void gemm_wide_kernel(GemmArgs a) {
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     u32x4 bh[2][WN], bl[2][WN], A[2][WMF];
+    i32x8 A8[2], B8[WN];
     uint2 acur[WMF], anext[WMF];
     read_a(0, acur);
     read_b(0, 0, bh[0], bl[0]);
     decode(acur, 0, A[0]);
+    if constexpr (F8) decode8(acur, 0, A8[0]);
 
     int st = 0;  // stage of chunk ch
     for (int ch = 0; ch < nch; ++ch) {
@@ -1095,16 +1253,19 @@ __global__ __launch_bounds__(256) void gemm_wide_kernel(GemmArgs a) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int cs = j & 1, ns = cs ^ 1;
+        if constexpr (F8) {
+          if (j == 0) read_b8(st, B8);  // this chunk's lo fragments, used by all four steps
+        }
         if (j < 3) {
           read_b(st, j + 1, bh[ns], bl[ns]);
           decode(acur, j + 1, A[ns]);
+          if constexpr (F8) decode8(acur, j + 1, A8[ns]);
         } else {
           // own copies of chunk ch+1 done (the NSTAGE-2 later chunks may
           // still be in flight) and own LDS reads of this chunk done; then
-          // every wave's
-          // (a plain s_barrier: a workgroup fence here would wait for
-          // every copy in flight)
-          __builtin_amdgcn_s_waitcnt(((NSTAGE - 2) * CHUNK_OPS) | (0x7 << 4) | (0x0 << 8));
+          // every wave's (a plain s_barrier: a workgroup fence here would
+          // wait for every copy in flight)
+          __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0((NSTAGE - 2) * CHUNK_OPS));
           read_a(st1, anext);  // this wave's own copies: no barrier needed
           asm volatile("s_barrier" ::: "memory");
           // LDS reads before the copies: a read issued after a
@@ -1112,20 +1273,29 @@ __global__ __launch_bounds__(256) void gemm_wide_kernel(GemmArgs a) {
           read_b(st1, 0, bh[ns], bl[ns]);
           dma(ch + NSTAGE, st);
           decode(anext, 0, A[ns]);
+          if constexpr (F8) decode8(anext, 0, A8[ns]);
         }
 #pragma unroll
         for (int fn = 0; fn < WN; ++fn)
 #pragma unroll
           for (int fm = 0; fm < WMF; ++fm) acc[fm][fn] = mfma16<PREC>(A[cs][fm], bh[cs][fn], acc[fm][fn]);
+        if constexpr (!F8) {
 #pragma unroll
-        for (int fn = 0; fn < WN; ++fn)
+          for (int fn = 0; fn < WN; ++fn)
 #pragma unroll
-          for (int fm = 0; fm < WMF; ++fm) acc[fm][fn] = mfma16<PREC>(A[cs][fm], bl[cs][fn], acc[fm][fn]);
+            for (int fm = 0; fm < WMF; ++fm) acc[fm][fn] = mfma16<PREC>(A[cs][fm], bl[cs][fn], acc[fm][fn]);
+        } else {
+#pragma unroll
+          for (int fn = 0; fn < WN; ++fn)
+            acc[j][fn] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A8[cs], B8[fn], acc[j][fn], 0, 0, 0, 127,
+                                                                         0, bscale[fn]);
+        }
         // issue order: copies and LDS reads early, each behind one
-        // matrix-core instruction, then the decode, three VALU ops per MFMA
+        // matrix-core instruction, then the decode, a few VALU ops per MFMA
+        constexpr int NDS0 = F8 ? 2 * WN : 0;  // lo fragment reads at step 0
         if (j == 3) {
 #pragma unroll
-          for (int q = 0; q < 2 * WN + WMF; ++q) {
+          for (int q = 0; q < DS_STEP + WMF; ++q) {
             __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // DS read
             __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
           }
@@ -1136,20 +1306,20 @@ __global__ __launch_bounds__(256) void gemm_wide_kernel(GemmArgs a) {
             __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);  // VALU
           }
 #pragma unroll
-          for (int q = 0; q < 32 - CHUNK_OPS - 2 * WN - WMF; ++q) {
+          for (int q = 0; q < MFMA_STEP - CHUNK_OPS - DS_STEP - WMF; ++q) {
             __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
             __builtin_amdgcn_sched_group_barrier(0x002, 6, 0);  // VALU
           }
         } else {
 #pragma unroll
-          for (int q = 0; q < 2 * WN; ++q) {
+          for (int q = 0; q < DS_STEP + (j == 0 ? NDS0 : 0); ++q) {
             __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // DS read
             __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
           }
 #pragma unroll
-          for (int q = 0; q < 32 - 2 * WN; ++q) {
+          for (int q = 0; q < MFMA_STEP - DS_STEP - (j == 0 ? NDS0 : 0); ++q) {
             __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
-            __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);  // VALU
+            __builtin_amdgcn_sched_group_barrier(0x002, F8 ? 5 : 3, 0);  // VALU
           }
         }
         __builtin_amdgcn_sched_barrier(0);
@@ -1272,20 +1442,26 @@ int wgemm_tile() { return kWShape; }
 
 template <int PREC, int MODE>
 static const void* gemm_fn(int idx) {
-  switch (idx) {
-    case 0:  // the wide kernel exists for the 16-bit split forms; FP32 uses shape 1
-      if constexpr (PREC != kFP32) return (const void*)gemm_wide_kernel<PREC, MODE>;
-      return (const void*)gemm_kernel<PREC, 8, 2, 4, MODE>;
-    case 1: return (const void*)gemm_kernel<PREC, 8, 2, 4, MODE>;
-    case 2: return (const void*)gemm_kernel<PREC, 4, 2, 4, MODE>;
-    case 3: return (const void*)gemm_kernel<PREC, 8, 1, 4, MODE>;
-    case 4: return (const void*)gemm_kernel<PREC, 8, 2, 2, MODE>;
-    case 5: return (const void*)gemm_kernel<PREC, 8, 2, 1, MODE>;
+  if constexpr (PREC == kSplit8) {
+    (void)idx;  // the FP8 lo form exists only as the wide kernel
+    return (const void*)gemm_wide_kernel<PREC, MODE>;
+  } else {
+    switch (idx) {
+      case 0:  // the wide kernel exists for the split forms; FP32 uses shape 1
+        if constexpr (PREC != kFP32) return (const void*)gemm_wide_kernel<PREC, MODE>;
+        return (const void*)gemm_kernel<PREC, 8, 2, 4, MODE>;
+      case 1: return (const void*)gemm_kernel<PREC, 8, 2, 4, MODE>;
+      case 2: return (const void*)gemm_kernel<PREC, 4, 2, 4, MODE>;
+      case 3: return (const void*)gemm_kernel<PREC, 8, 1, 4, MODE>;
+      case 4: return (const void*)gemm_kernel<PREC, 8, 2, 2, MODE>;
+      case 5: return (const void*)gemm_kernel<PREC, 8, 2, 1, MODE>;
+    }
+    return nullptr;
   }
-  return nullptr;
 }
 
 static TileShape effective_shape(int idx, int prec) {
+  if (prec == kSplit8) return kShapes[0];
   if (idx == 0 && prec == kFP32) return kShapes[1];
   return kShapes[idx];
 }
@@ -1294,7 +1470,15 @@ TileShape tile_shape_for(int idx, int prec) { return effective_shape(idx, prec);
 static const void* gemm_fn_any(int idx, int prec, int mode) {
   if (prec == kSplit) return mode == kRaw ? gemm_fn<kSplit, kRaw>(idx) : gemm_fn<kSplit, kTest>(idx);
   if (prec == kSplit16) return mode == kRaw ? gemm_fn<kSplit16, kRaw>(idx) : gemm_fn<kSplit16, kTest>(idx);
+  if (prec == kSplit8) return mode == kRaw ? gemm_fn<kSplit8, kRaw>(idx) : gemm_fn<kSplit8, kTest>(idx);
   return mode == kRaw ? gemm_fn<kFP32, kRaw>(idx) : gemm_fn<kFP32, kTest>(idx);
+}
+
+int tile_alias(int idx, int prec) {
+  const void* fn = gemm_fn_any(idx, prec, kTest);
+  for (int i = 0; i < idx; ++i)
+    if (gemm_fn_any(i, prec, kTest) == fn) return i;
+  return idx;
 }
 
 int gemm_grid(int idx, int prec, int mode, int n_cu) {
@@ -1331,15 +1515,21 @@ hipError_t launch_cov_operands(const double* Q, int64_t n, int64_t n_pad, int q,
 
 hipError_t launch_prep(const void* Y, int y_fp64, int64_t ldy, int64_t n, int64_t n_pad, int64_t P,
                        const double* Q, int q, int prec, void* yop, float* scale, float* invny, float* cw,
-                       int32_t* flags, hipStream_t s) {
+                       uint8_t* lscale, int32_t* flags, hipStream_t s) {
   hipLaunchKernelGGL(prep_kernel, dim3((unsigned)P), dim3(kPrepThreads), 0, s, Y, y_fp64, ldy, n, n_pad, P, Q,
-                     q, prec, yop, scale, invny, cw, flags);
+                     q, prec, yop, scale, invny, cw, lscale, flags);
   return hipGetLastError();
 }
 
 hipError_t launch_set_operand(const float* V, int64_t ldv, int64_t n, int64_t n_pad, int64_t P, int prec,
-                              void* yop, hipStream_t s) {
-  hipLaunchKernelGGL(set_operand_kernel, dim3(1024), dim3(256), 0, s, V, ldv, n, n_pad, P, prec, yop);
+                              void* yop, uint8_t* lscale, hipStream_t s) {
+  if (prec == kSplit8) {
+    hipLaunchKernelGGL(set_lscale_kernel, dim3((unsigned)P), dim3(kPrepThreads), 0, s, V, ldv, n, lscale);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(set_operand_kernel, dim3(1024), dim3(256), 0, s, V, ldv, n, n_pad, P, prec, yop,
+                     (const uint8_t*)lscale);
   return hipGetLastError();
 }
 

@@ -101,7 +101,7 @@ struct tgw_covariates {
   int64_t n = 0, n_pad = 0;
   int q = 0, n_chunks = 0;
   double* Q = nullptr;       // [q][n_pad]
-  void* wop[kNumPrec] = {nullptr, nullptr, nullptr};  // Q^T g operand block per precision
+  void* wop[kNumPrec] = {};  // Q^T g operand block per precision (the FP8 form uses the FP16 split's)
 };
 
 struct tgw_panel {
@@ -114,6 +114,7 @@ struct tgw_panel {
   float* invny = nullptr;
   float* cw = nullptr;
   float2* table = nullptr;
+  uint8_t* lscale = nullptr;  // FP8 lo form: E8M0 scale per column
 };
 
 struct tgw_plan {
@@ -223,7 +224,7 @@ extern "C" tgw_status tgw_fit_covariates(int64_t n_samples, int32_t n_cov, const
   if (e == hipSuccess) e = dmalloc(&rdiag, (size_t)cov->q);
   if (e == hipSuccess) e = dmalloc(&flags, 2);
   for (int k = 0; k < kNumPrec; ++k)
-    if (e == hipSuccess) e = hipMalloc(&cov->wop[k], (size_t)cov->n_chunks * kBlockBytes);
+    if (e == hipSuccess && wprec(k) == k) e = hipMalloc(&cov->wop[k], (size_t)cov->n_chunks * kBlockBytes);
   if (e == hipSuccess) e = hipMemsetAsync(flags, 0, 2 * sizeof(int32_t), s);
   if (e == hipSuccess) e = launch_qr(d_C, ldc, n_samples, cov->n_pad, cov->q, X, cov->Q, rdiag, flags, s);
   if (e == hipSuccess)
@@ -269,6 +270,7 @@ extern "C" void tgw_panel_free(tgw_panel* p) {
   (void)hipFree(p->invny);
   (void)hipFree(p->cw);
   (void)hipFree(p->table);
+  (void)hipFree(p->lscale);
   delete p;
 }
 
@@ -279,7 +281,7 @@ extern "C" tgw_status tgw_prepare_phenotypes(const tgw_covariates* cov, int64_t 
   if (!out) return fail(TGW_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
   if (!cov || !d_Y) return fail(TGW_ERR_INVALID_ARG, "NULL argument");
-  if (prec != TGW_PREC_FP32 && prec != TGW_PREC_SPLIT && prec != TGW_PREC_SPLIT_F16)
+  if (prec != TGW_PREC_FP32 && prec != TGW_PREC_SPLIT && prec != TGW_PREC_SPLIT_F16 && prec != TGW_PREC_SPLIT_F8)
     return fail(TGW_ERR_INVALID_ARG, "bad precision");
   if (y_is_fp64 != 0 && y_is_fp64 != 1) return fail(TGW_ERR_INVALID_ARG, "y_is_fp64 must be 0 or 1");
   if (n_pheno < 1) return fail(TGW_ERR_SHAPE, "n_pheno must be >= 1");
@@ -293,11 +295,16 @@ extern "C" tgw_status tgw_prepare_phenotypes(const tgw_covariates* cov, int64_t 
   p->cov = cov;
   p->P = n_pheno;
   p->P_pad = round_up(n_pheno, kColBlock);
-  p->prec = prec == TGW_PREC_SPLIT ? kSplit : prec == TGW_PREC_SPLIT_F16 ? kSplit16 : kFP32;
+  p->prec = prec == TGW_PREC_SPLIT       ? kSplit
+            : prec == TGW_PREC_SPLIT_F16 ? kSplit16
+            : prec == TGW_PREC_SPLIT_F8  ? kSplit8
+                                         : kFP32;
   p->df = cov->n - cov->q - 1;
   int32_t* flags = nullptr;
-  const size_t op_bytes = (size_t)(p->P_pad / kColBlock) * cov->n_chunks * kBlockBytes;
+  const size_t op_bytes = (size_t)(p->P_pad / kColBlock) * cov->n_chunks * block_bytes(p->prec);
   hipError_t e = hipMalloc(&p->yop, op_bytes);
+  if (e == hipSuccess) e = dmalloc(&p->lscale, p->P_pad);
+  if (e == hipSuccess) e = hipMemsetAsync(p->lscale, 127, p->P_pad, s);
   if (e == hipSuccess) e = dmalloc(&p->scale, p->P_pad);
   if (e == hipSuccess) e = dmalloc(&p->invny, p->P_pad);
   if (e == hipSuccess) e = dmalloc(&p->cw, (size_t)p->P_pad * kSlots);
@@ -310,7 +317,7 @@ extern "C" tgw_status tgw_prepare_phenotypes(const tgw_covariates* cov, int64_t 
   if (e == hipSuccess) e = hipMemsetAsync(flags, 0, sizeof(int32_t), s);
   if (e == hipSuccess)
     e = launch_prep(d_Y, y_is_fp64, ldy, cov->n, cov->n_pad, n_pheno, cov->Q, cov->q, p->prec, p->yop, p->scale,
-                    p->invny, p->cw, flags, s);
+                    p->invny, p->cw, p->lscale, flags, s);
   if (e == hipSuccess) e = launch_table(p->table, (double)p->df, s);
   int32_t hf = 0;
   if (e == hipSuccess) e = hipMemcpyAsync(&hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s);
@@ -342,7 +349,8 @@ extern "C" tgw_status tgw_debug_set_operand(tgw_panel* p, const float* d_V, int6
   TGW_GUARD_BEGIN
   if (!p || !d_V) return fail(TGW_ERR_INVALID_ARG, "NULL argument");
   if (ldv < p->cov->n) return fail(TGW_ERR_SHAPE, "ldv < n");
-  HIP_TRY(launch_set_operand(d_V, ldv, p->cov->n, p->cov->n_pad, p->P, p->prec, p->yop, (hipStream_t)stream));
+  HIP_TRY(launch_set_operand(d_V, ldv, p->cov->n, p->cov->n_pad, p->P, p->prec, p->yop, p->lscale,
+                             (hipStream_t)stream));
   return TGW_OK;
   TGW_GUARD_END
 }
@@ -466,14 +474,14 @@ extern "C" tgw_status tgw_plan_create(const tgw_panel* const* panels, int32_t n_
     const int64_t nb = p->P_pad / kColBlock;
     for (int64_t b = 0; b < nb; ++b) {
       ColBlock c{};
-      c.op = (const char*)p->yop + (size_t)b * pl->n_chunks * kBlockBytes;
+      c.op = (const char*)p->yop + (size_t)b * pl->n_chunks * block_bytes(pl->prec);
       c.panel = j;
       c.col0 = (int32_t)(b * kColBlock);
       c.ncol = (int32_t)std::min<int64_t>(kColBlock, p->P - b * kColBlock);
       cbm.push_back(c);
     }
     ColBlock w{};
-    w.op = (const char*)p->cov->wop[pl->prec];
+    w.op = (const char*)p->cov->wop[wprec(pl->prec)];
     w.panel = j;
     w.col0 = j * kSlots;
     w.ncol = kSlots;
@@ -483,6 +491,7 @@ extern "C" tgw_status tgw_plan_create(const tgw_panel* const* panels, int32_t n_
     d.invny = p->invny;
     d.cw = p->cw;
     d.table = p->table;
+    d.lscale = p->lscale;
     d.n_pheno = p->P;
     d.df = (float)p->df;
     d.sqrt_df = (float)std::sqrt((double)p->df);
@@ -518,7 +527,7 @@ extern "C" tgw_status tgw_plan_create(const tgw_panel* const* panels, int32_t n_
     return hip_fail(e, "tgw_plan_create");
   }
   for (int i = 0; i < n_tile_shapes(); ++i) pl->grid_main.push_back(gemm_grid(i, pl->prec, kTest, pl->n_cu));
-  pl->grid_w = gemm_grid(wgemm_tile(), pl->prec, kRaw, pl->n_cu);
+  pl->grid_w = gemm_grid(wgemm_tile(), wprec(pl->prec), kRaw, pl->n_cu);
   if (o.tile >= 0) {
     pl->tile = o.tile;
   } else {
@@ -612,10 +621,10 @@ static hipError_t enqueue_block_stats(tgw_plan* pl, const ScanCall& c, int64_t m
   a.n_mtiles = (int)((nm + ws.tm() - 1) / ws.tm());
   a.raw_out = pl->wws;
   a.raw_ld = (int64_t)pl->n_panels * kSlots;
-  e = launch_gemm(wgemm_tile(), pl->prec, kRaw, a, pl->grid_w, s);
+  e = launch_gemm(wgemm_tile(), wprec(pl->prec), kRaw, a, pl->grid_w, s);
   if (e != hipSuccess) return e;
   return launch_finalize(pl->mstat, pl->wws, pl->invh, nm, pl->n_panels,
-                         pl->prec == kSplit16 ? 1.0f / kF16Scale : 1.0f, s);
+                         f16_scaled(pl->prec) ? 1.0f / kF16Scale : 1.0f, s);
 }
 
 static hipError_t enqueue_main(tgw_plan* pl, const ScanCall& c, int64_t m0, int64_t nm, int tile, hipStream_t s) {
@@ -715,6 +724,7 @@ extern "C" tgw_status tgw_plan_autotune(tgw_plan* pl, const uint8_t* d_geno, int
   double best_t = 1e300;
   hipError_t err = hipSuccess;
   for (int t = 0; t < n_tile_shapes() && err == hipSuccess; ++t) {
+    if (tile_alias(t, pl->prec) != t) continue;  // same kernel as an earlier shape
     err = enqueue_main(pl, c, m_begin, nm, t, s);  // warm-up
     if (err != hipSuccess) break;
     const int reps = 3;

@@ -36,11 +36,13 @@ ERR_TAIL_OVERFLOW = 8
 PREC_FP32 = 0
 PREC_SPLIT = 1
 PREC_SPLIT_F16 = 2
-F16_SCALE = 4096.0  # the FP16 split stores 2^12 times the operand
+PREC_SPLIT_F8 = 3
+F16_SCALE = 4096.0  # the FP16 forms store 2^12 times the operand
 CODE_DOSAGE = 0
 CODE_PLINK_BED = 1
-_PREC = {"fp32": PREC_FP32, "split": PREC_SPLIT, "split16": PREC_SPLIT_F16,
-         PREC_FP32: PREC_FP32, PREC_SPLIT: PREC_SPLIT, PREC_SPLIT_F16: PREC_SPLIT_F16}
+_PREC = {"fp32": PREC_FP32, "split": PREC_SPLIT, "split16": PREC_SPLIT_F16, "split8": PREC_SPLIT_F8,
+         PREC_FP32: PREC_FP32, PREC_SPLIT: PREC_SPLIT, PREC_SPLIT_F16: PREC_SPLIT_F16,
+         PREC_SPLIT_F8: PREC_SPLIT_F8}
 
 OUTPUT_NAMES = ("r", "beta", "se", "t", "nlog10p")
 
@@ -176,9 +178,9 @@ class Covariates:
         _check(_cov_q(self._h, _ptr(out), self.n_samples, _stream(stream)), "tgw_covariates_q")
         return out.t()
 
-    def __del__(self):
+    def __del__(self, _free=_cov_free):  # bound early: module globals are gone at interpreter exit
         if getattr(self, "_h", None):
-            _cov_free(self._h)
+            _free(self._h)
             self._h = None
 
 
@@ -220,9 +222,9 @@ class Panel:
         _check(_dbg_set_operand(self._h, _ptr(Vc), ld, _stream(stream)), "tgw_debug_set_operand")
         torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
 
-    def __del__(self):
+    def __del__(self, _free=_panel_free):  # bound early: module globals are gone at interpreter exit
         if getattr(self, "_h", None):
-            _panel_free(self._h)
+            _free(self._h)
             self._h = None
 
 
@@ -343,9 +345,9 @@ class Plan:
                "tgw_debug_marker_stats")
         return shift, mean
 
-    def __del__(self):
+    def __del__(self, _free=_plan_free):  # bound early: module globals are gone at interpreter exit
         if getattr(self, "_h", None):
-            _plan_free(self._h)
+            _free(self._h)
             self._h = None
 
 
@@ -357,9 +359,9 @@ class Graph:
     def launch(self, stream=None):
         _check(_graph_launch(self._h, _stream(stream)), "tgw_graph_launch")
 
-    def __del__(self):
+    def __del__(self, _free=_graph_free):  # bound early: module globals are gone at interpreter exit
         if getattr(self, "_h", None):
-            _graph_free(self._h)
+            _free(self._h)
             self._h = None
 
 

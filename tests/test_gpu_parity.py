@@ -16,8 +16,9 @@ from tests.gpu_common import R_TOL, compare, cohort_arrays, decode_codes, gpu_sc
 
 pytestmark = pytest.mark.gpu
 
-PRECS = ["split", "split16", "fp32"]
-GRID = {"split": 64, "split16": 512, "fp32": 64}
+PRECS = ["split", "split16", "split8", "fp32"]
+GRID = {"split": 64, "split16": 512, "split8": 512, "fp32": 64}
+F16_FORMS = ("split16", "split8")  # operands stored as 2^12 y
 
 
 @pytest.fixture(scope="module")
@@ -58,8 +59,8 @@ def test_contraction_exact_integers(tgw, precision, n, m, p):
     want_shift = np.rint(grid * codes.mean(axis=1)) / grid
     want_shift[5] = 0.0  # degenerate (monomorphic) markers are not re-centred
     np.testing.assert_array_equal(shift, want_shift)
-    if precision == "split16":
-        S = S / tgw.F16_SCALE  # the FP16 split stores 2^12 times the operand
+    if precision in F16_FORMS:
+        S = S / tgw.F16_SCALE  # the FP16 forms store 2^12 times the operand
     A = codes.astype(np.float64) - shift[:, None]
     want = A @ V.astype(np.float64)
     assert np.array_equal(want, want.astype(np.float32).astype(np.float64))  # exactly representable
@@ -81,7 +82,7 @@ def test_contraction_missing_value(tgw, precision):
     plan = tgw.Plan([panel])
     g = torch.from_numpy(pack_codes_np(codes, row_bytes_for(n))).cuda()
     S = plan.debug_contract(g).cpu().numpy().astype(np.float64)
-    if precision == "split16":
+    if precision in F16_FORMS:
         S = S / tgw.F16_SCALE
     shift, mean = [x.cpu().numpy() for x in plan.debug_marker_stats(g)]
     obs = codes < 3
@@ -90,7 +91,7 @@ def test_contraction_missing_value(tgw, precision):
     vm = mu - shift
     if precision == "split":
         vm_op, bound = _bf16_round(vm), 2.0 ** -16
-    elif precision == "split16":
+    elif precision in F16_FORMS:
         vm_op, bound = vm.astype(np.float16).astype(np.float64), 2.0 ** -21
     else:
         vm_op, bound = vm.astype(np.float32).astype(np.float64), 2.0 ** -30
@@ -100,6 +101,50 @@ def test_contraction_missing_value(tgw, precision):
     want = A @ V.astype(np.float64)
     scale = np.abs(A) @ np.abs(V.astype(np.float64)) + 1.0
     assert np.max(np.abs(S - want) / scale) < 1e-6
+
+
+def _e4m3(x: np.ndarray) -> np.ndarray:
+    """Round to OCP FP8 E4M3 (nearest even) and back, via torch's CPU conversion."""
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(torch.float8_e4m3fn).to(
+        torch.float64).numpy()
+
+
+def test_contraction_fp8_lo_term(tgw):
+    """FP16 hi + FP8 lo form on non-integer operands: the contraction equals
+    A16 @ hi + A8 @ lo8 * 2^-s, with hi = fp16(2^12 v), lo8 = e4m3((2^12 v - hi) 2^s)
+    for the column's shift s, A16 the re-centred genotypes (exact in FP16) and
+    A8 = e4m3(A16).  The lo term is ~2^-12 of the total, so a wrong sample
+    order, decode or scale in the FP8 pass fails the 1e-6 bound."""
+    say("case: FP8 lo term of the FP16 hi + FP8 lo contraction")
+    rng = np.random.default_rng(61)
+    n, m, p = 1000, 700, 70
+    codes = rng.integers(0, 3, size=(m, n)).astype(np.uint8)
+    codes[rng.random((m, n)) < 0.03] = 3
+    V = (rng.standard_normal((n, p)) * np.exp(rng.uniform(-3, 3, size=p))[None, :] / np.sqrt(n)).astype(np.float32)
+    cov = tgw.fit_covariates(None, n_samples=n)
+    panel = tgw.prepare_phenotypes(cov, torch.randn(n, p, dtype=torch.float32, device="cuda"), "split8")
+    panel.debug_set_operand(torch.from_numpy(V).cuda())
+    plan = tgw.Plan([panel])
+    g = torch.from_numpy(pack_codes_np(codes, row_bytes_for(n))).cuda()
+    S = plan.debug_contract(g).cpu().numpy().astype(np.float64)
+    shift, _ = [x.cpu().numpy() for x in plan.debug_marker_stats(g)]
+    obs = codes < 3
+    mu = np.where(obs, codes, 0).sum(1) / obs.sum(1)
+    A16 = np.where(obs, codes - shift[:, None], (mu - shift)[:, None].astype(np.float16).astype(np.float64))
+    A8 = _e4m3(np.where(obs, codes - shift[:, None], (mu - shift)[:, None]))
+    vs = V.astype(np.float64) * tgw.F16_SCALE
+    hi = vs.astype(np.float16).astype(np.float64)
+    lo = vs - hi
+    mx = np.abs(lo).max(axis=0)
+    sh = np.where(mx > 0, np.floor(np.log2(448.0 / np.where(mx > 0, mx, 1.0))), 0.0)
+    lo8 = _e4m3(lo * 2.0 ** sh[None, :]) * 2.0 ** -sh[None, :]
+    want = A16 @ hi + A8 @ lo8
+    scale = np.abs(A16) @ np.abs(vs)
+    err = np.max(np.abs(S - want) / scale)
+    lo_part = np.max(np.abs(A8 @ lo8) / scale)
+    say(f"fp8 lo term: max rel err {err:.3g}, lo term up to {lo_part:.3g} of the scale")
+    assert lo_part > 1e-5  # the lo term is visible at this tolerance
+    assert err < 1e-6
 
 
 # ---------------------------------------------------------------------------
@@ -305,17 +350,18 @@ def test_cfg2_sampled_blocks(tgw, precision):
     compare(res[0], ref, ref["df"], f"cfg2 {precision} ")
 
 
-def test_cfg3_bench_configuration(tgw):
+@pytest.mark.parametrize("precision", ["split", "split8"])
+def test_cfg3_bench_configuration(tgw, precision):
     """Precision form at full size (N=23,000, M=1,000,000, P=2,048) in the benchmark's
     launch configuration; sampled rows are checked against the oracle."""
     spec = cohort_spec("cfg3")
     M, n = spec.n_markers, spec.n_samples
-    say("case: cfg3 full scan, sampled parity")
+    say(f"case: cfg3 full scan {precision}, sampled parity")
     C, Y = panel_inputs(spec)
     g = torch.empty((M, row_bytes_for(n)), dtype=torch.uint8, device="cuda")
     packed_rows_torch(spec, 0, M, "cuda", out=g, chunk=8192)
     cov = tgw.fit_covariates(torch.from_numpy(C).cuda())
-    panel = tgw.prepare_phenotypes(cov, torch.from_numpy(Y).cuda(), "split")
+    panel = tgw.prepare_phenotypes(cov, torch.from_numpy(Y).cuda(), precision)
     plan = tgw.Plan([panel])
     outs = tgw.make_outputs([panel.n_pheno], M, names=("r", "nlog10p"))
     plan.scan(g, outs)
@@ -328,7 +374,7 @@ def test_cfg3_bench_configuration(tgw):
                           pack_codes_np(geno_codes_np(spec, rows), row_bytes_for(n)))
     codes = geno_codes_np(spec, rows)
     ref = oracle_scan(codes, C, Y)
-    compare(got, ref, ref["df"], "cfg3 split ")
+    compare(got, ref, ref["df"], f"cfg3 {precision} ")
 
 
 def test_cfg5_batching_form_sampled(tgw):
