@@ -121,8 +121,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cfg3", choices=["cfg2", "cfg3", "cfg4", "cfg5"])
-    ap.add_argument("--precision", default="split", choices=["split", "split16", "split8", "fp32"])
-    ap.add_argument("--beside", default="split16,fp32",
+    ap.add_argument("--precision", default="split8", choices=["split", "split16", "split8", "fp32"])
+    ap.add_argument("--beside", default="split,split16,fp32",
                     help="other precisions timed on the same workload (comma list, '' = none)")
     ap.add_argument("--beside-steps", type=int, default=1)
     ap.add_argument("--markers", type=int, default=0, help="override M (0 = the workload's)")
@@ -283,7 +283,10 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved / peak,
             "traffic": traffic,
-            "kernel": "gemm_kernel (contraction + fused epilogue)",
+            "kernel": ("gemm_wide_kernel" if info["tile"] == 0 and args.precision != "fp32" else "gemm_kernel")
+                      + " (contraction + fused epilogue)",
+            "peak_basis": "dense 16-bit MFMA; the FP8 lo pass of split8 runs at twice that rate"
+                          if args.precision == "split8" else "dense MFMA of the operand type",
             "algorithmic_flops_per_launch": flops_per_launch,
             "avg_launch_ms": avg_launch_s * 1e3,
         },

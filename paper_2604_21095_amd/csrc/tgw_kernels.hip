@@ -1067,6 +1067,8 @@ typedef int i32x8 __attribute__((ext_vector_type(8)));
 
 // s_waitcnt immediate: vmcnt(vm), lgkmcnt(0), expcnt unconstrained
 constexpr int waitcnt_vm_lgkm0(int vm) { return (vm & 15) | ((vm >> 4) << 14) | (0x7 << 4); }
+// vmcnt(vm) only (expcnt and lgkmcnt unconstrained)
+constexpr int waitcnt_vm_only(int vm) { return waitcnt_vm_lgkm0(vm) | (0xF << 8); }
 
 template <int PREC, int MODE>
 __global__ __launch_bounds__(256) void gemm_wide_kernel(GemmArgs a) {
@@ -1085,7 +1087,6 @@ __global__ __launch_bounds__(256) void gemm_wide_kernel(GemmArgs a) {
   constexpr int A_OPS = A_BYTES / (NT * 16);
   constexpr int CHUNK_OPS = B_OPS + A_OPS;
   constexpr int HI_MFMA = F8 ? WMF * WN : 2 * WMF * WN;  // 16-bit MFMA per step
-  constexpr int MFMA_STEP = HI_MFMA + (F8 ? WN : 0);
   constexpr int DS_STEP = F8 ? WN : 2 * WN;              // fragment reads per step
   static_assert(NW * WMF * 32 * 32 * 4 <= LDS_BYTES, "epilogue staging must fit");
   static_assert((NSTAGE - 2) * CHUNK_OPS < 64, "vmcnt range");
@@ -1180,13 +1181,19 @@ __global__ __launch_bounds__(256) void gemm_wide_kernel(GemmArgs a) {
     // whole 16-byte rows, this lane's half picked in registers (paired
     // 8-byte reads would be fused into one read that the compiler then holds
     // until every direct-to-LDS copy in flight has landed)
-    auto read_a = [&](int st, uint2* dst) {
+    auto read_a_raw = [&](int st, u32x4* raw) {
       const char* ab = smem + st * STAGE_BYTES + B_BYTES + wave * (WMF * 32 * 16);
 #pragma unroll
-      for (int fm = 0; fm < WMF; ++fm) {
-        const u32x4 v = *(const u32x4*)(ab + (fm * 32 + r32) * 16);
-        dst[fm] = h ? make_uint2(v[2], v[3]) : make_uint2(v[0], v[1]);
-      }
+      for (int fm = 0; fm < WMF; ++fm) raw[fm] = *(const u32x4*)(ab + (fm * 32 + r32) * 16);
+    };
+    auto pick_a = [&](const u32x4* raw, uint2* dst) {
+#pragma unroll
+      for (int fm = 0; fm < WMF; ++fm) dst[fm] = h ? make_uint2(raw[fm][2], raw[fm][3]) : make_uint2(raw[fm][0], raw[fm][1]);
+    };
+    auto read_a = [&](int st, uint2* dst) {
+      u32x4 raw[WMF];
+      read_a_raw(st, raw);
+      pick_a(raw, dst);
     };
     // 16-bit values of K16 step j: two per dword via the per-marker table
     auto decode = [&](const uint2* src2, int j, u32x4* A) {
@@ -1242,10 +1249,15 @@ __global__ __launch_bounds__(256) void gemm_wide_kernel(GemmArgs a) {
     u32x4 bh[2][WN], bl[2][WN], A[2][WMF];
     i32x8 A8[2], B8[WN];
     uint2 acur[WMF], anext[WMF];
+    u32x4 araw[WMF];  // FP8 form: the next chunk's code rows, read a step early
     read_a(0, acur);
     read_b(0, 0, bh[0], bl[0]);
     decode(acur, 0, A[0]);
     if constexpr (F8) decode8(acur, 0, A8[0]);
+
+    // the prologue's reads are complete before the loop; saying so keeps
+    // the compiler from waiting for all LDS reads at the loop head
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0), vmcnt and expcnt unconstrained
 
     int st = 0;  // stage of chunk ch
     for (int ch = 0; ch < nch; ++ch) {
@@ -1256,24 +1268,29 @@ __global__ __launch_bounds__(256) void gemm_wide_kernel(GemmArgs a) {
         if constexpr (F8) {
           if (j == 0) read_b8(st, B8);  // this chunk's lo fragments, used by all four steps
         }
+        if (F8 && j == 2) {
+          // the next chunk's codes are this wave's own copies: they need
+          // only its own copy of chunk ch+1 to have landed, not the barrier
+          __builtin_amdgcn_s_waitcnt(waitcnt_vm_only((NSTAGE - 2) * CHUNK_OPS));
+          read_a_raw(st1, araw);  // this lane's halves are picked at step 3
+        }
         if (j < 3) {
           read_b(st, j + 1, bh[ns], bl[ns]);
           decode(acur, j + 1, A[ns]);
-          if constexpr (F8) decode8(acur, j + 1, A8[ns]);
         } else {
           // own copies of chunk ch+1 done (the NSTAGE-2 later chunks may
           // still be in flight) and own LDS reads of this chunk done; then
           // every wave's (a plain s_barrier: a workgroup fence here would
           // wait for every copy in flight)
           __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0((NSTAGE - 2) * CHUNK_OPS));
-          read_a(st1, anext);  // this wave's own copies: no barrier needed
+          if constexpr (!F8) read_a(st1, anext);  // this wave's own copies: no barrier needed
+          if constexpr (F8) pick_a(araw, anext);
           asm volatile("s_barrier" ::: "memory");
           // LDS reads before the copies: a read issued after a
           // direct-to-LDS load is held until that load completes
           read_b(st1, 0, bh[ns], bl[ns]);
-          dma(ch + NSTAGE, st);
+          if constexpr (!F8) dma(ch + NSTAGE, st);  // the FP8 form copies beside its lo MFMAs
           decode(anext, 0, A[ns]);
-          if constexpr (F8) decode8(anext, 0, A8[ns]);
         }
 #pragma unroll
         for (int fn = 0; fn < WN; ++fn)
@@ -1284,16 +1301,22 @@ __global__ __launch_bounds__(256) void gemm_wide_kernel(GemmArgs a) {
           for (int fn = 0; fn < WN; ++fn)
 #pragma unroll
             for (int fm = 0; fm < WMF; ++fm) acc[fm][fn] = mfma16<PREC>(A[cs][fm], bl[cs][fn], acc[fm][fn]);
-        } else {
-#pragma unroll
-          for (int fn = 0; fn < WN; ++fn)
-            acc[j][fn] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A8[cs], B8[fn], acc[j][fn], 0, 0, 0, 127,
-                                                                         0, bscale[fn]);
         }
         // issue order: copies and LDS reads early, each behind one
         // matrix-core instruction, then the decode, a few VALU ops per MFMA
-        constexpr int NDS0 = F8 ? 2 * WN : 0;  // lo fragment reads at step 0
-        if (j == 3) {
+        if (j == 3 && F8) {
+#pragma unroll
+          for (int q = 0; q < DS_STEP; ++q) {
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // DS read
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+            __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);  // VALU
+          }
+#pragma unroll
+          for (int q = 0; q < HI_MFMA - DS_STEP; ++q) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+            __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);  // VALU
+          }
+        } else if (j == 3) {
 #pragma unroll
           for (int q = 0; q < DS_STEP + WMF; ++q) {
             __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // DS read
@@ -1306,23 +1329,69 @@ __global__ __launch_bounds__(256) void gemm_wide_kernel(GemmArgs a) {
             __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);  // VALU
           }
 #pragma unroll
-          for (int q = 0; q < MFMA_STEP - CHUNK_OPS - DS_STEP - WMF; ++q) {
+          for (int q = 0; q < HI_MFMA - CHUNK_OPS - DS_STEP - WMF; ++q) {
             __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
             __builtin_amdgcn_sched_group_barrier(0x002, 6, 0);  // VALU
           }
         } else {
+          if (F8 && j == 0) {  // plus the chunk's lo fragment reads
 #pragma unroll
-          for (int q = 0; q < DS_STEP + (j == 0 ? NDS0 : 0); ++q) {
-            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // DS read
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
-          }
+            for (int q = 0; q < 3 * WN; ++q) {
+              __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // DS read
+              __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+              __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);  // VALU
+            }
 #pragma unroll
-          for (int q = 0; q < MFMA_STEP - DS_STEP - (j == 0 ? NDS0 : 0); ++q) {
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
-            __builtin_amdgcn_sched_group_barrier(0x002, F8 ? 5 : 3, 0);  // VALU
+            for (int q = 0; q < HI_MFMA - 3 * WN; ++q) {
+              __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+              __builtin_amdgcn_sched_group_barrier(0x002, 12, 0);  // VALU
+            }
+          } else {
+            constexpr int VPD = F8 ? 3 : 0, VREST = F8 ? 5 : 3;
+#pragma unroll
+            for (int q = 0; q < DS_STEP; ++q) {
+              __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // DS read
+              __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+              if (VPD) __builtin_amdgcn_sched_group_barrier(0x002, VPD, 0);  // VALU
+            }
+#pragma unroll
+            for (int q = 0; q < HI_MFMA - DS_STEP; ++q) {
+              __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+              __builtin_amdgcn_sched_group_barrier(0x002, VREST, 0);  // VALU
+            }
           }
         }
         __builtin_amdgcn_sched_barrier(0);
+        if constexpr (F8) {
+          // FP8 lo term of fragment fm = j over the whole chunk, after the
+          // step's FP16 work (its operands were read at step 0); the decode
+          // of the next fragment's e4m3 values rides along
+          if (j < 3) {
+            decode8(acur, j + 1, A8[ns]);
+          } else {
+            dma(ch + NSTAGE, st);  // the stage of chunk ch is free since the barrier
+            decode8(anext, 0, A8[ns]);
+          }
+#pragma unroll
+          for (int fn = 0; fn < WN; ++fn)
+            acc[j][fn] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A8[cs], B8[fn], acc[j][fn], 0, 0, 0, 127,
+                                                                         0, bscale[fn]);
+          if (j == 3) {
+#pragma unroll
+            for (int q = 0; q < WN; ++q) {
+              __builtin_amdgcn_sched_group_barrier(0x010, CHUNK_OPS / WN, 0);  // VMEM (direct-to-LDS)
+              __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);               // MFMA
+              __builtin_amdgcn_sched_group_barrier(0x002, 12, 0);              // VALU
+            }
+          } else {
+#pragma unroll
+            for (int q = 0; q < WN; ++q) {
+              __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+              __builtin_amdgcn_sched_group_barrier(0x002, 6, 0);  // VALU
+            }
+          }
+          __builtin_amdgcn_sched_barrier(0);
+        }
       }
 #pragma unroll
       for (int fm = 0; fm < WMF; ++fm) acur[fm] = anext[fm];
