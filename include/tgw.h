@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define TGW_ABI_VERSION 1
+#define TGW_ABI_VERSION 2
 
 typedef enum {
   TGW_OK = 0,
@@ -110,7 +110,18 @@ typedef struct tgw_graph tgw_graph;           /* a captured tgw_scan call     */
  * Degenerate markers (no observed call, monomorphic among observed calls, or
  * ||g_res||^2 <= 1e-4 ||g_c||^2, i.e. the covariates explain 99.99 % of the
  * marker's variance) and degenerate phenotypes (residual norm <= 1e-12 of the
- * centred norm) give NaN in every output. */
+ * centred norm) give NaN in every output.
+ *   best     optional reduced output (Methods 2.2, after Eq. 3: the
+ *            statistics feed locus ranking and phenotype-level
+ *            prioritization): device array of
+ *            n_pheno entries holding, for each phenotype p, the test with the
+ *            largest -log10 p over every marker scanned into it, packed as
+ *            (IEEE bits of that -log10 p) << 32 | (0xffffffff - marker), with
+ *            the absolute marker index (the smallest one among equal maxima).
+ *            The caller zeroes it before the first scan; scans merge by
+ *            maximum, so marker ranges may be split over calls (markers
+ *            < 2^32).  NaN tests never enter; 0 means none.  Independent of
+ *            the dense arrays, which may all be NULL. */
 typedef struct {
   float* r;
   float* beta;
@@ -118,7 +129,17 @@ typedef struct {
   float* t;
   float* nlog10p;
   int64_t ld;
+  unsigned long long* best;
 } tgw_outputs;
+
+/* One entry of a thresholded hit list (see tgw_plan_set_hits). */
+typedef struct {
+  int64_t marker;  /* absolute marker index */
+  int32_t panel;   /* panel index in the plan */
+  int32_t pheno;   /* phenotype column of that panel */
+  float nlog10p;   /* -log10 p (FP64-finished for |t| > 40) */
+  float r;         /* partial correlation */
+} tgw_hit;
 
 /* Scan plan options; zero-initialise and set what you need. */
 typedef struct {
@@ -204,6 +225,11 @@ tgw_status tgw_plan_autotune(tgw_plan* plan, const uint8_t* d_geno, int64_t n_ma
  * a missing call as mu - c rounded to the operand type (error <= 2^-16 in
  * BF16, 2^-21 in FP16); the intercept of the covariate projection removes c
  * exactly.
+ * Results are deterministic run to run.  A scan split into several marker
+ * ranges gives bitwise the same outputs as one call when every boundary is a
+ * multiple of 512 markers from m_begin (any boundary for FP32 and the 16-bit
+ * split forms; the FP16 hi + FP8 lo form orders its FP32 accumulation by a
+ * marker's row in the 512-marker tile).
  * Asynchronous: enqueues kernels on `stream`, allocates nothing and does not
  * synchronize; capturable in a HIP graph.  The plan's workspace is reused, so
  * calls with the same plan must not run concurrently on different streams.
@@ -213,6 +239,18 @@ tgw_status tgw_plan_autotune(tgw_plan* plan, const uint8_t* d_geno, int64_t n_ma
 tgw_status tgw_scan(tgw_plan* plan, const uint8_t* d_geno, int64_t n_markers, int64_t row_bytes,
                     tgw_geno_code code, int64_t m_begin, int64_t m_end, const tgw_outputs* outs,
                     void* stream);
+/* Thresholded hit list (reduced output; Methods 2.2, after Eq. 3: ranking
+ * associated loci)
+ * for the following tgw_scan calls on this plan and for graphs captured
+ * afterwards: every test with -log10 p >= threshold is appended to d_hits
+ * (device, `capacity` entries) at index atomicAdd(d_count, 1), in no
+ * particular order.  Entries past `capacity` are dropped but still counted:
+ * *d_count > capacity after a scan means the list is truncated.  The caller
+ * owns both buffers and zeroes *d_count; successive scans keep appending.
+ * d_hits == NULL turns the list off.  The autotuner never appends. */
+tgw_status tgw_plan_set_hits(tgw_plan* plan, tgw_hit* d_hits, int64_t capacity, unsigned long long* d_count,
+                             float threshold);
+
 /* Synchronizes `stream` and reports device errors / tail overflow of the
  * last tgw_scan on this plan; n_tail receives the number of tail tests. */
 tgw_status tgw_plan_check(tgw_plan* plan, void* stream, int64_t* n_tail);

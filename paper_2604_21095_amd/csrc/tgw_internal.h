@@ -73,6 +73,24 @@ struct OutDev {
   float* t;
   float* nl;
   int64_t ld;
+  unsigned long long* best;  // per column: (bits of max -log10 p) << 32 | (0xffffffff - marker)
+};
+
+// thresholded hit list (layout of tgw_hit)
+struct Hit {
+  int64_t marker;
+  int32_t panel;
+  int32_t pheno;
+  float nl;
+  float r;
+};
+
+struct HitDev {
+  Hit* entries;               // NULL: no hit list
+  unsigned long long* count;
+  int64_t capacity;
+  float threshold;
+  int32_t pad;
 };
 
 // one 32-column block of the virtual concatenation of all panels' columns
@@ -89,7 +107,7 @@ struct TailEntry {
   int32_t panel;
   int32_t col;
   float r;
-  float pad;
+  int32_t hit;  // index of the test's entry in the hit list, -1 if none
 };
 
 struct TailDev {
@@ -119,6 +137,8 @@ struct GemmArgs {
   float* raw_out;        // RAW mode destination
   int64_t raw_ld;
   TailDev tail;
+  HitDev hits;
+  int64_t m_begin;   // absolute index of output row 0
 };
 
 struct StatsArgs {
@@ -156,7 +176,8 @@ hipError_t launch_finalize(const MarkerStat* ms, float* wws, float* invh, int64_
                            hipStream_t s);
 hipError_t launch_bind(const BindArgs& a, hipStream_t s);
 hipError_t launch_tail_reset(TailDev t, hipStream_t s);
-hipError_t launch_tail(TailDev t, const PanelDev* panels, const OutDev* outs, hipStream_t s);
+hipError_t launch_tail(TailDev t, const PanelDev* panels, const OutDev* outs, HitDev hits, int64_t m_begin,
+                       hipStream_t s);
 hipError_t launch_debug_stats(const MarkerStat* ms, int64_t nm, double* shift, double* mean, hipStream_t s);
 
 // main contraction; `tile` selects one of the compiled tile shapes

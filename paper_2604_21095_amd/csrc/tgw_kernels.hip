@@ -658,7 +658,15 @@ __global__ void tail_reset_kernel(TailDev t) {
   if (threadIdx.x == 0 && blockIdx.x == 0) t.count[0] = 0ull;
 }
 
-__global__ void tail_kernel(TailDev t, const PanelDev* __restrict__ panels, const OutDev* __restrict__ outs) {
+// per-column best test: max -log10 p in the high word, the complement of
+// the marker index in the low word (so equal maxima keep the first marker)
+__device__ inline unsigned long long best_pack(float nl, int64_t marker) {
+  return ((unsigned long long)__float_as_uint(nl > 0.f ? nl : 0.f) << 32) |
+         (unsigned long long)(0xffffffffu - (uint32_t)marker);
+}
+
+__global__ void tail_kernel(TailDev t, const PanelDev* __restrict__ panels, const OutDev* __restrict__ outs,
+                            HitDev hits, int64_t m_begin) {
   const unsigned long long cnt = t.count[0];
   const int64_t n = cnt < (unsigned long long)t.capacity ? (int64_t)cnt : t.capacity;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n;
@@ -668,8 +676,11 @@ __global__ void tail_kernel(TailDev t, const PanelDev* __restrict__ panels, cons
     const double r = (double)e.r;
     const double tt = r * sqrt(df / ((1.0 - r) * (1.0 + r)));
     const double lnp = ln_p_two_sided(tt, df);
+    const float nl = (float)(-lnp / M_LN10);
     const OutDev o = outs[e.panel];
-    o.nl[e.row * o.ld + e.col] = (float)(-lnp / M_LN10);
+    if (o.nl) o.nl[e.row * o.ld + e.col] = nl;
+    if (o.best) atomicMax(o.best + e.col, best_pack(nl, m_begin + e.row));  // replaces the lower bound
+    if (e.hit >= 0) hits.entries[e.hit].nl = nl;
   }
 }
 
@@ -720,10 +731,14 @@ __device__ __forceinline__ f32x16 mfma16(const u32x4& a, const u32x4& b, const f
   }
 }
 
-// -log10 p, t, beta, SE and r of one test; writes the requested outputs
-__device__ __forceinline__ void epilogue_one(float S, float invh, float invny, float sp, const PanelDev& pd,
-                                             const OutDev& od, int64_t o, int64_t row, int j, int64_t p,
-                                             const TailDev& tail) {
+// -log10 p, t, beta, SE and r of one test; writes the requested outputs,
+// appends the test to the hit list when it reaches the threshold, and
+// returns its -log10 p for the per-column best (NaN when undefined; for
+// |t| > 40 the table's value at 40, a lower bound that the FP64 tail kernel
+// replaces)
+__device__ __forceinline__ float epilogue_one(float S, float invh, float invny, float sp, const PanelDev& pd,
+                                              const OutDev& od, int64_t o, int64_t row, int j, int64_t p,
+                                              const TailDev& tail, const HitDev& hits, int64_t marker) {
   float r = S * invh * invny;
   if (r > 1.0f) r = 1.0f;
   if (r < -1.0f) r = -1.0f;
@@ -733,31 +748,90 @@ __device__ __forceinline__ void epilogue_one(float S, float invh, float invny, f
   if (od.beta) gstore(od.beta + o, r * sp * invh);
   if (od.se) gstore(od.se + o, sp * invh * sqrtf(omr2) * pd.inv_sqrt_df);
   if (od.t) gstore(od.t + o, t);
-  if (od.nl) {
-    const float at = fabsf(t);
-    float nl;
-    if (at <= kTMax) {
-      nl = table_nlog10p(pd.table, at);
-    } else if (at != at) {
-      nl = at;  // NaN
+  if (!(od.nl || od.best || hits.entries)) return __builtin_nanf("");
+  const float at = fabsf(t);
+  float nl, track;
+  bool to_tail = false;
+  if (at <= kTMax) {
+    nl = track = table_nlog10p(pd.table, at);
+  } else if (at != at) {
+    nl = track = at;  // NaN
+  } else if (at == INFINITY) {
+    nl = track = INFINITY;
+  } else {
+    track = table_nlog10p(pd.table, kTMax);  // lower bound until the tail kernel runs
+    nl = INFINITY;
+    to_tail = true;
+  }
+  int32_t hit = -1;
+  if (hits.entries && track >= hits.threshold) {
+    const unsigned long long idx = atomicAdd(hits.count, 1ull);
+    if (idx < (unsigned long long)hits.capacity) {
+      Hit h;
+      h.marker = marker;
+      h.panel = j;
+      h.pheno = (int32_t)p;
+      h.nl = to_tail ? track : nl;
+      h.r = r;
+      hits.entries[idx] = h;
+      hit = (int32_t)idx;
+    }
+  }
+  if (to_tail) {
+    const unsigned long long idx = atomicAdd(tail.count, 1ull);
+    if (idx < (unsigned long long)tail.capacity) {
+      TailEntry e;
+      e.row = row;
+      e.panel = j;
+      e.col = (int32_t)p;
+      e.r = r;
+      e.hit = hit;
+      tail.entries[idx] = e;
     } else {
-      nl = INFINITY;
-      if (at != INFINITY) {
-        const unsigned long long idx = atomicAdd(tail.count, 1ull);
-        if (idx < (unsigned long long)tail.capacity) {
-          TailEntry e;
-          e.row = row;
-          e.panel = j;
-          e.col = (int32_t)p;
-          e.r = r;
-          e.pad = 0.f;
-          tail.entries[idx] = e;
-        } else {
-          nl = table_nlog10p(pd.table, kTMax);  // lower bound
-        }
+      nl = track;  // lower bound
+    }
+  }
+  if (od.nl) gstore(od.nl + o, nl);
+  return track;
+}
+
+// finish one 32-column block of a wave's staged accumulators (stage holds
+// rows 0 .. 32*WMF-1 of the wave's fragments, 32 columns each): lanes run
+// along columns, two rows at a time; the per-column best over the rows is
+// reduced in registers and merged with one atomic per column
+template <int WMF>
+__device__ __forceinline__ void finish_block(const float* stage, const GemmArgs& a, const ColBlock& blk,
+                                             int64_t rowbase, int h, int r32) {
+  const int j = blk.panel;
+  const PanelDev pd = a.panels[j];
+  const OutDev od = a.outs[j];
+  const int64_t p = blk.col0 + r32;
+  const bool colok = r32 < blk.ncol;
+  const float invny = colok ? gload<float>(pd.invny + p) : 0.f;
+  const float sp = colok ? gload<float>(pd.scale + p) : 0.f;
+  float bv = -1.0f;
+  int64_t bm = 0;
+  for (int rr = h; rr < WMF * 32; rr += 2) {
+    const int64_t mr = rowbase + rr;
+    if (colok && mr < a.nm) {
+      const float invh = gload<float>(a.invh + mr * a.n_panels + j);
+      const int64_t row = a.out_row0 + mr;
+      const float nl = epilogue_one(stage[rr * 32 + r32], invh, invny, sp, pd, od, row * od.ld + p, row, j, p,
+                                    a.tail, a.hits, a.m_begin + row);
+      if (nl > bv) {
+        bv = nl;
+        bm = a.m_begin + row;
       }
     }
-    gstore(od.nl + o, nl);
+  }
+  if (od.best) {  // uniform: one panel per column block
+    const float ov = __shfl_xor(bv, 32);
+    const int64_t om = __shfl_xor(bm, 32);
+    if (ov > bv || (ov == bv && om < bm)) {
+      bv = ov;
+      bm = om;
+    }
+    if (h == 0 && colok && bv >= 0.0f) atomicMax(od.best + p, best_pack(bv, bm));
   }
 }
 
@@ -1018,22 +1092,7 @@ __global__ __launch_bounds__(NW * 64) void gemm_kernel(GemmArgs a) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const ColBlock blk = a.cblocks[cb];
-        const int j = blk.panel;
-        const PanelDev pd = a.panels[j];
-        const OutDev od = a.outs[j];
-        const int64_t p = blk.col0 + r32;
-        const bool colok = r32 < blk.ncol;
-        const float invny = colok ? gload<float>(pd.invny + p) : 0.f;
-        const float sp = colok ? gload<float>(pd.scale + p) : 0.f;
-        for (int rr = h; rr < WMF * 32; rr += 2) {
-          const int64_t mr = rowbase + rr;
-          if (colok && mr < a.nm) {
-            const float invh = gload<float>(a.invh + mr * a.n_panels + j);
-            const int64_t row = a.out_row0 + mr;
-            epilogue_one(stage[rr * 32 + r32], invh, invny, sp, pd, od, row * od.ld + p, row, j, p, a.tail);
-          }
-        }
+        finish_block<WMF>(stage, a, a.cblocks[cb], rowbase, h, r32);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -1465,22 +1524,7 @@ __global__ __launch_bounds__(256) void gemm_wide_kernel(GemmArgs a) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const ColBlock blk = a.cblocks[cb];
-        const int j = blk.panel;
-        const PanelDev pd = a.panels[j];
-        const OutDev od = a.outs[j];
-        const int64_t p = blk.col0 + r32;
-        const bool colok = r32 < blk.ncol;
-        const float invny = colok ? gload<float>(pd.invny + p) : 0.f;
-        const float sp = colok ? gload<float>(pd.scale + p) : 0.f;
-        for (int rr = h; rr < WMF * 32; rr += 2) {
-          const int64_t mr = rowbase + rr;
-          if (colok && mr < a.nm) {
-            const float invh = gload<float>(a.invh + mr * a.n_panels + j);
-            const int64_t row = a.out_row0 + mr;
-            epilogue_one(stage[rr * 32 + r32], invh, invny, sp, pd, od, row * od.ld + p, row, j, p, a.tail);
-          }
-        }
+        finish_block<WMF>(stage, a, a.cblocks[cb], rowbase, h, r32);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -1631,8 +1675,9 @@ hipError_t launch_tail_reset(TailDev t, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_tail(TailDev t, const PanelDev* panels, const OutDev* outs, hipStream_t s) {
-  hipLaunchKernelGGL(tail_kernel, dim3(64), dim3(64), 0, s, t, panels, outs);
+hipError_t launch_tail(TailDev t, const PanelDev* panels, const OutDev* outs, HitDev hits, int64_t m_begin,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(tail_kernel, dim3(64), dim3(64), 0, s, t, panels, outs, hits, m_begin);
   return hipGetLastError();
 }
 

@@ -135,6 +135,7 @@ struct tgw_plan {
   TailEntry* tail_entries = nullptr;
   unsigned long long* tail_count = nullptr;
   int64_t tail_cap = 0;
+  HitDev hits{};  // thresholded hit list of the following scans (entries NULL: off)
   int tile = 0;
   std::vector<int> grid_main;  // per tile shape
   int grid_w = 0;
@@ -572,8 +573,9 @@ static tgw_status check_call(const tgw_plan* pl, const ScanCall& c, bool need_ou
     if (!c.outs) return fail(TGW_ERR_INVALID_ARG, "outs is NULL");
     for (int j = 0; j < pl->n_panels; ++j) {
       const tgw_outputs& o = c.outs[j];
-      const bool any = o.r || o.beta || o.se || o.t || o.nlog10p;
-      if (any && o.ld < pl->panels[j]->P) return fail(TGW_ERR_SHAPE, "outs[j].ld < n_pheno of panel j");
+      const bool dense = o.r || o.beta || o.se || o.t || o.nlog10p;
+      if (dense && o.ld < pl->panels[j]->P) return fail(TGW_ERR_SHAPE, "outs[j].ld < n_pheno of panel j");
+      if (o.best && c.m_end > 0xffffffffll) return fail(TGW_ERR_SHAPE, "best needs marker indices below 2^32");
     }
   }
   return TGW_OK;
@@ -596,6 +598,8 @@ static GemmArgs base_args(const tgw_plan* pl, const ScanCall& c, int64_t m0, int
   a.tail.entries = pl->tail_entries;
   a.tail.count = pl->tail_count;
   a.tail.capacity = pl->tail_cap;
+  a.hits = pl->hits;
+  a.m_begin = c.m_begin;
   return a;
 }
 
@@ -658,7 +662,7 @@ static hipError_t enqueue_bind(tgw_plan* pl, const tgw_outputs* outs, hipStream_
     b.count = std::min(kMaxPanelsPerBind, pl->n_panels - j0);
     for (int i = 0; i < b.count; ++i) {
       const tgw_outputs& o = outs[j0 + i];
-      b.outs[i] = OutDev{o.r, o.beta, o.se, o.t, o.nlog10p, o.ld};
+      b.outs[i] = OutDev{o.r, o.beta, o.se, o.t, o.nlog10p, o.ld, o.best};
     }
     hipError_t e = launch_bind(b, s);
     if (e != hipSuccess) return e;
@@ -674,8 +678,25 @@ static hipError_t enqueue_scan(tgw_plan* pl, const ScanCall& c, hipStream_t s) {
     e = enqueue_block_stats(pl, c, m0, nm, s);
     if (e == hipSuccess) e = enqueue_main(pl, c, m0, nm, pl->tile, s);
   }
-  if (e == hipSuccess) e = launch_tail(TailDev{pl->tail_entries, pl->tail_count, pl->tail_cap}, pl->d_panels, pl->d_outs, s);
+  if (e == hipSuccess)
+    e = launch_tail(TailDev{pl->tail_entries, pl->tail_count, pl->tail_cap}, pl->d_panels, pl->d_outs, pl->hits,
+                    c.m_begin, s);
   return e;
+}
+
+extern "C" tgw_status tgw_plan_set_hits(tgw_plan* pl, tgw_hit* d_hits, int64_t capacity,
+                                        unsigned long long* d_count, float threshold) {
+  if (!pl) return fail(TGW_ERR_INVALID_ARG, "plan is NULL");
+  if (!d_hits) {
+    pl->hits = HitDev{};
+    return TGW_OK;
+  }
+  if (!d_count) return fail(TGW_ERR_INVALID_ARG, "d_count is NULL");
+  if (capacity < 0) return fail(TGW_ERR_INVALID_ARG, "negative capacity");
+  if (!(threshold == threshold)) return fail(TGW_ERR_INVALID_ARG, "threshold is NaN");
+  static_assert(sizeof(tgw_hit) == sizeof(Hit), "tgw_hit layout");
+  pl->hits = HitDev{(Hit*)d_hits, d_count, capacity, threshold, 0};
+  return TGW_OK;
 }
 
 extern "C" tgw_status tgw_scan(tgw_plan* pl, const uint8_t* d_geno, int64_t n_markers, int64_t row_bytes,
@@ -717,6 +738,13 @@ extern "C" tgw_status tgw_plan_autotune(tgw_plan* pl, const uint8_t* d_geno, int
   HIP_TRY(enqueue_bind(pl, outs, s));
   HIP_TRY(launch_tail_reset(TailDev{pl->tail_entries, pl->tail_count, pl->tail_cap}, s));
   HIP_TRY(enqueue_block_stats(pl, c, m_begin, nm, s));
+  const HitDev saved_hits = pl->hits;  // repeated timing runs must not append hits
+  pl->hits = HitDev{};
+  struct Restore {
+    tgw_plan* p;
+    HitDev h;
+    ~Restore() { p->hits = h; }
+  } restore{pl, saved_hits};
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));

@@ -49,7 +49,16 @@ OUTPUT_NAMES = ("r", "beta", "se", "t", "nlog10p")
 
 class Outputs(ctypes.Structure):
     _fields_ = [("r", ctypes.c_void_p), ("beta", ctypes.c_void_p), ("se", ctypes.c_void_p),
-                ("t", ctypes.c_void_p), ("nlog10p", ctypes.c_void_p), ("ld", ctypes.c_int64)]
+                ("t", ctypes.c_void_p), ("nlog10p", ctypes.c_void_p), ("ld", ctypes.c_int64),
+                ("best", ctypes.c_void_p)]
+
+
+class Hit(ctypes.Structure):
+    _fields_ = [("marker", ctypes.c_int64), ("panel", ctypes.c_int32), ("pheno", ctypes.c_int32),
+                ("nlog10p", ctypes.c_float), ("r", ctypes.c_float)]
+
+
+HIT_DTYPE_BYTES = ctypes.sizeof(Hit)  # 24
 
 
 class PlanOptions(ctypes.Structure):
@@ -91,6 +100,7 @@ _autotune = _sig("tgw_plan_autotune", ctypes.c_int, _vp, _vp, _i64, _i64, ctypes
                  ctypes.POINTER(Outputs), _vp, ctypes.POINTER(ctypes.c_double))
 _scan = _sig("tgw_scan", ctypes.c_int, _vp, _vp, _i64, _i64, ctypes.c_int, _i64, _i64, ctypes.POINTER(Outputs), _vp)
 _plan_check = _sig("tgw_plan_check", ctypes.c_int, _vp, _vp, ctypes.POINTER(_i64))
+_plan_set_hits = _sig("tgw_plan_set_hits", ctypes.c_int, _vp, _vp, _i64, _vp, ctypes.c_float)
 _profile = _sig("tgw_plan_profile", ctypes.c_int, _vp, _i32)
 _profile_read = _sig("tgw_plan_profile_read", ctypes.c_int, _vp, _vp, ctypes.POINTER(ctypes.c_double),
                      ctypes.POINTER(_i64))
@@ -269,7 +279,42 @@ def _outs_array(outs: Sequence[Dict[str, torch.Tensor]], panels, n_rows: int):
             ld = t.stride(0)
             setattr(arr[j], name, t.data_ptr())
         arr[j].ld = ld if ld is not None else pan.n_pheno
+        b = o.get("best") if o else None
+        if b is not None:
+            _dev_check(b)
+            if b.dtype != torch.int64 or b.dim() != 1 or not b.is_contiguous() or b.shape[0] < pan.n_pheno:
+                raise ValueError(f"best of panel {j} must be a contiguous int64 vector of n_pheno entries")
+            arr[j].best = b.data_ptr()
     return arr
+
+
+def make_best(panel_sizes: Sequence[int]) -> List[torch.Tensor]:
+    """Zeroed per-phenotype best-test accumulators (one int64 per column)."""
+    return [torch.zeros(p, dtype=torch.int64, device="cuda") for p in panel_sizes]
+
+
+def unpack_best(best: torch.Tensor):
+    """(max -log10 p, marker) per column from a best accumulator; marker -1 where none."""
+    v = best.cpu().numpy().view("uint64")
+    nl = (v >> 32).astype("uint32").view("float32")
+    marker = (0xFFFFFFFF - (v & 0xFFFFFFFF)).astype("int64")
+    marker[v == 0] = -1
+    return nl, marker
+
+
+def make_hits(capacity: int):
+    """Device hit list of `capacity` entries and its zeroed counter."""
+    return (torch.zeros((capacity, HIT_DTYPE_BYTES // 4), dtype=torch.int32, device="cuda"),
+            torch.zeros(1, dtype=torch.int64, device="cuda"))
+
+
+def read_hits(hits: torch.Tensor, count: torch.Tensor):
+    """Hit list as numpy arrays (marker, panel, pheno, nlog10p, r) and the raw count."""
+    n = int(count.item())
+    raw = hits[: min(n, hits.shape[0])].cpu().numpy()
+    marker = raw[:, 0:2].copy().view("int64")[:, 0]
+    return {"marker": marker, "panel": raw[:, 2].copy(), "pheno": raw[:, 3].copy(),
+            "nlog10p": raw[:, 4].copy().view("float32"), "r": raw[:, 5].copy().view("float32"), "count": n}
 
 
 class Plan:
@@ -301,6 +346,20 @@ class Plan:
         g, nm, rb, code, m0, m1 = self._args(geno, m_begin, m_end, code)
         arr = _outs_array(outs, self.panels, m1 - m0)
         _check(_scan(self._h, g, nm, rb, code, m0, m1, arr, _stream(stream)), "tgw_scan")
+
+    def set_hits(self, hits: Optional[torch.Tensor], count: Optional[torch.Tensor] = None, threshold: float = 7.3):
+        """Thresholded hit list for the following scans (make_hits); None turns it off."""
+        if hits is None:
+            _check(_plan_set_hits(self._h, None, 0, None, ctypes.c_float(0.0)), "tgw_plan_set_hits")
+            self._hits = None
+            return
+        _dev_check(hits)
+        _dev_check(count)
+        if not hits.is_contiguous() or hits.element_size() * hits.shape[-1] != HIT_DTYPE_BYTES:
+            raise ValueError("hits must come from make_hits")
+        _check(_plan_set_hits(self._h, _ptr(hits), hits.shape[0], _ptr(count), ctypes.c_float(threshold)),
+               "tgw_plan_set_hits")
+        self._hits = (hits, count)  # keep the buffers alive while the plan refers to them
 
     def check(self, stream=None) -> int:
         n = _i64()

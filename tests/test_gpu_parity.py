@@ -271,12 +271,15 @@ def test_errors(tgw):
 # ---------------------------------------------------------------------------
 # determinism, resume, graphs, batching
 # ---------------------------------------------------------------------------
-def test_determinism_resume_graph(tgw):
+@pytest.mark.parametrize("precision,cut", [("split", 1234), ("split8", 1024)])
+def test_determinism_resume_graph(tgw, precision, cut):
+    """Repeat, resume over two ranges (for the FP8 lo form at a 512-marker
+    boundary, see tgw_scan), and graph replay give bitwise the same outputs."""
     spec = cohort_spec("cfg1")
-    say("case: determinism / resume / graph replay")
+    say(f"case: determinism / resume / graph replay {precision}")
     codes, packed, C, Y = cohort_arrays(spec, np.arange(3000))
     cov = tgw.fit_covariates(torch.from_numpy(C).cuda())
-    panel = tgw.prepare_phenotypes(cov, torch.from_numpy(Y).cuda(), "split")
+    panel = tgw.prepare_phenotypes(cov, torch.from_numpy(Y).cuda(), precision)
     plan = tgw.Plan([panel])
     g = torch.from_numpy(packed).cuda()
     a = tgw.scan(plan, g)
@@ -284,8 +287,8 @@ def test_determinism_resume_graph(tgw):
     for k in a[0]:
         assert torch.equal(torch.nan_to_num(a[0][k], nan=7.0), torch.nan_to_num(b[0][k], nan=7.0)), k
     # resume: two marker ranges
-    p1 = tgw.scan(plan, g, m_begin=0, m_end=1234)
-    p2 = tgw.scan(plan, g, m_begin=1234, m_end=3000)
+    p1 = tgw.scan(plan, g, m_begin=0, m_end=cut)
+    p2 = tgw.scan(plan, g, m_begin=cut, m_end=3000)
     for k in a[0]:
         joined = torch.cat([p1[0][k], p2[0][k]])
         assert torch.equal(torch.nan_to_num(joined, nan=7.0), torch.nan_to_num(a[0][k], nan=7.0)), k
