@@ -1117,10 +1117,16 @@ __global__ __launch_bounds__(NW * 64) void gemm_kernel(GemmArgs a) {
 // next chunk has landed and every wave is done with this chunk's stage,
 // which is refilled at once.
 //
-// Forms: the 16-bit splits run 32 MFMA 32x32x16 per step (hi and lo terms);
-// FP16 hi + FP8 lo runs 16 FP16 MFMA per step plus, for the step's marker
-// fragment fm = j, 4 block-scaled FP8 MFMA 32x32x64 over the whole chunk
-// (E8M0 scale of each column's lo term on the B side).
+// Forms: the 16-bit splits run 2 x WMF x 4 MFMA 32x32x16 per step (hi and lo
+// terms); FP16 hi + FP8 lo runs WMF x 4 FP16 MFMA per step plus a quarter of
+// the chunk's block-scaled FP8 MFMA 32x32x64 (E8M0 scale of each column's lo
+// term on the B side): with WMF = 4 those of marker fragment j, with WMF = 2
+// those of column block j.
+//
+// Shapes: NW = 4, WMF = 4 (one wave per SIMD, 128 x 128 per wave, 256 AGPR
+// accumulators) or NW = 8, WMF = 2 (two waves per SIMD, 64 x 128 per wave),
+// so that one wave's genotype decode and epilogue overlap the other wave's
+// matrix-core work.
 // ---------------------------------------------------------------------------
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 
@@ -1129,11 +1135,13 @@ constexpr int waitcnt_vm_lgkm0(int vm) { return (vm & 15) | ((vm >> 4) << 14) | 
 // vmcnt(vm) only (expcnt and lgkmcnt unconstrained)
 constexpr int waitcnt_vm_only(int vm) { return waitcnt_vm_lgkm0(vm) | (0xF << 8); }
 
-template <int PREC, int MODE>
-__global__ __launch_bounds__(256) void gemm_wide_kernel(GemmArgs a) {
+template <int PREC, int MODE, int NW, int WMF>
+__global__ __launch_bounds__(NW * 64) void gemm_wide_kernel(GemmArgs a) {
   static_assert(PREC != kFP32, "the wide kernel runs the split forms");
+  static_assert(NW * WMF == 16 && (WMF == 4 || WMF == 2), "512-marker tiles");
   constexpr bool F8 = PREC == kSplit8;
-  constexpr int NW = 4, WMF = 4, WN = 4, NT = 256;
+  constexpr bool W2 = WMF == 2;  // two waves per SIMD
+  constexpr int WN = 4, NT = NW * 64;
   constexpr int TM = NW * WMF * 32;
   constexpr int BB = block_bytes(PREC);
   constexpr int NSTAGE = F8 ? 4 : 3;
@@ -1286,18 +1294,19 @@ __global__ __launch_bounds__(256) void gemm_wide_kernel(GemmArgs a) {
         if constexpr (!F8) bl[fn] = *(const u32x4*)(tile + fn * BB + (2048 + j * 512 + lane * 8) * 2);
       }
     };
-    auto read_b8 = [&](int st, i32x8* B8) {
+    auto read_b8_one = [&](int st, int fn, i32x8& B8f) {
       const char* tile = smem + st * STAGE_BYTES;
+      const u32x4 p0 = *(const u32x4*)(tile + fn * BB + 4096 + lane * 16);
+      const u32x4 p1 = *(const u32x4*)(tile + fn * BB + 4096 + 1024 + lane * 16);
 #pragma unroll
-      for (int fn = 0; fn < WN; ++fn) {
-        const u32x4 p0 = *(const u32x4*)(tile + fn * BB + 4096 + lane * 16);
-        const u32x4 p1 = *(const u32x4*)(tile + fn * BB + 4096 + 1024 + lane * 16);
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          B8[fn][t] = (int)p0[t];
-          B8[fn][4 + t] = (int)p1[t];
-        }
+      for (int t = 0; t < 4; ++t) {
+        B8f[t] = (int)p0[t];
+        B8f[4 + t] = (int)p1[t];
       }
+    };
+    auto read_b8 = [&](int st, i32x8* B8) {
+#pragma unroll
+      for (int fn = 0; fn < WN; ++fn) read_b8_one(st, fn, B8[fn]);
     };
 
     // prologue: chunks 0..NSTAGE-1 requested, chunk 0 awaited
@@ -1312,7 +1321,7 @@ __global__ __launch_bounds__(256) void gemm_wide_kernel(GemmArgs a) {
     read_a(0, acur);
     read_b(0, 0, bh[0], bl[0]);
     decode(acur, 0, A[0]);
-    if constexpr (F8) decode8(acur, 0, A8[0]);
+    if constexpr (F8 && !W2) decode8(acur, 0, A8[0]);
 
     // the prologue's reads are complete before the loop; saying so keeps
     // the compiler from waiting for all LDS reads at the loop head
@@ -1324,8 +1333,15 @@ __global__ __launch_bounds__(256) void gemm_wide_kernel(GemmArgs a) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int cs = j & 1, ns = cs ^ 1;
-        if constexpr (F8) {
+        if constexpr (F8 && !W2) {
           if (j == 0) read_b8(st, B8);  // this chunk's lo fragments, used by all four steps
+        }
+        if constexpr (F8 && W2) {
+          read_b8_one(st, j, B8[j]);  // column block j's lo fragment, used by this step
+          if (j == 0) {
+#pragma unroll
+            for (int fm = 0; fm < WMF; ++fm) decode8(acur, fm, A8[fm]);  // both fragments, whole chunk
+          }
         }
         if (F8 && j == 2) {
           // the next chunk's codes are this wave's own copies: they need
@@ -1363,7 +1379,20 @@ __global__ __launch_bounds__(256) void gemm_wide_kernel(GemmArgs a) {
         }
         // issue order: copies and LDS reads early, each behind one
         // matrix-core instruction, then the decode, a few VALU ops per MFMA
-        if (j == 3 && F8) {
+        if (F8 && W2) {  // 8 FP16 MFMA; 4 hi + 2 lo fragment reads (+ 2 code rows at step 2)
+          constexpr int NDS = W2 ? WN + 2 : 0;
+#pragma unroll
+          for (int q = 0; q < NDS; ++q) {
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // DS read
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+            __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);  // VALU
+          }
+#pragma unroll
+          for (int q = 0; q < HI_MFMA - NDS; ++q) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+            __builtin_amdgcn_sched_group_barrier(0x002, 12, 0);  // VALU
+          }
+        } else if (j == 3 && F8) {
 #pragma unroll
           for (int q = 0; q < DS_STEP; ++q) {
             __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // DS read
@@ -1421,7 +1450,24 @@ __global__ __launch_bounds__(256) void gemm_wide_kernel(GemmArgs a) {
           }
         }
         __builtin_amdgcn_sched_barrier(0);
-        if constexpr (F8) {
+        if constexpr (F8 && W2) {
+          // FP8 lo term of column block j, both fragments, whole chunk
+          if (j == 3) dma(ch + NSTAGE, st);  // the stage of chunk ch is free since the barrier
+#pragma unroll
+          for (int fm = 0; fm < WMF; ++fm)
+            acc[fm][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A8[fm], B8[j], acc[fm][j], 0, 0, 0, 127,
+                                                                         0, bscale[j]);
+          if (j == 3) {
+#pragma unroll
+            for (int q = 0; q < WMF; ++q) {
+              __builtin_amdgcn_sched_group_barrier(0x010, CHUNK_OPS / WMF, 0);  // VMEM (direct-to-LDS)
+              __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                // MFMA
+              __builtin_amdgcn_sched_group_barrier(0x002, 8, 0);                // VALU
+            }
+          }
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        if constexpr (F8 && !W2) {
           // FP8 lo term of fragment fm = j over the whole chunk, after the
           // step's FP16 work (its operands were read at step 0); the decode
           // of the next fragment's e4m3 values rides along
@@ -1539,15 +1585,16 @@ __global__ __launch_bounds__(256) void gemm_wide_kernel(GemmArgs a) {
 // ---------------------------------------------------------------------------
 // {waves, 32-row fragments per wave, 32-column blocks per tile}
 static const TileShape kShapes[] = {
-    {4, 4, 4},  // 512 x 128, one wave per SIMD, direct-to-LDS operand copy (split only)
-    {8, 2, 4},  // 512 x 128
-    {4, 2, 4},  // 256 x 128
-    {8, 1, 4},  // 256 x 128, 8 waves
-    {8, 2, 2},  // 512 x 64
-    {8, 2, 1},  // 512 x 32 (Q^T g contraction)
+    {4, 4, 4},  // 0: 512 x 128, wide, one wave per SIMD (split forms)
+    {8, 2, 4},  // 1: 512 x 128, wide, two waves per SIMD (split forms)
+    {8, 2, 4},  // 2: 512 x 128
+    {4, 2, 4},  // 3: 256 x 128
+    {8, 1, 4},  // 4: 256 x 128, 8 waves
+    {8, 2, 2},  // 5: 512 x 64
+    {8, 2, 1},  // 6: 512 x 32 (Q^T g contraction)
 };
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
-constexpr int kWShape = 5;
+constexpr int kWShape = 6;
 
 int n_tile_shapes() { return kNumShapes - 1; }
 TileShape tile_shape(int idx) { return kShapes[idx]; }
@@ -1555,27 +1602,30 @@ int wgemm_tile() { return kWShape; }
 
 template <int PREC, int MODE>
 static const void* gemm_fn(int idx) {
-  if constexpr (PREC == kSplit8) {
-    (void)idx;  // the FP8 lo form exists only as the wide kernel
-    return (const void*)gemm_wide_kernel<PREC, MODE>;
+  if constexpr (PREC == kSplit8) {  // the FP8 lo form exists only as the wide kernel
+    if (idx == 1) return (const void*)gemm_wide_kernel<PREC, MODE, 8, 2>;
+    return (const void*)gemm_wide_kernel<PREC, MODE, 4, 4>;
   } else {
     switch (idx) {
-      case 0:  // the wide kernel exists for the split forms; FP32 uses shape 1
-        if constexpr (PREC != kFP32) return (const void*)gemm_wide_kernel<PREC, MODE>;
+      case 0:  // the wide kernels exist for the split forms; FP32 uses shape 2
+        if constexpr (PREC != kFP32) return (const void*)gemm_wide_kernel<PREC, MODE, 4, 4>;
         return (const void*)gemm_kernel<PREC, 8, 2, 4, MODE>;
-      case 1: return (const void*)gemm_kernel<PREC, 8, 2, 4, MODE>;
-      case 2: return (const void*)gemm_kernel<PREC, 4, 2, 4, MODE>;
-      case 3: return (const void*)gemm_kernel<PREC, 8, 1, 4, MODE>;
-      case 4: return (const void*)gemm_kernel<PREC, 8, 2, 2, MODE>;
-      case 5: return (const void*)gemm_kernel<PREC, 8, 2, 1, MODE>;
+      case 1:
+        if constexpr (PREC != kFP32) return (const void*)gemm_wide_kernel<PREC, MODE, 8, 2>;
+        return (const void*)gemm_kernel<PREC, 8, 2, 4, MODE>;
+      case 2: return (const void*)gemm_kernel<PREC, 8, 2, 4, MODE>;
+      case 3: return (const void*)gemm_kernel<PREC, 4, 2, 4, MODE>;
+      case 4: return (const void*)gemm_kernel<PREC, 8, 1, 4, MODE>;
+      case 5: return (const void*)gemm_kernel<PREC, 8, 2, 2, MODE>;
+      case 6: return (const void*)gemm_kernel<PREC, 8, 2, 1, MODE>;
     }
     return nullptr;
   }
 }
 
 static TileShape effective_shape(int idx, int prec) {
-  if (prec == kSplit8) return kShapes[0];
-  if (idx == 0 && prec == kFP32) return kShapes[1];
+  if (prec == kSplit8) return kShapes[idx == 1 ? 1 : 0];
+  if (idx <= 1 && prec == kFP32) return kShapes[2];
   return kShapes[idx];
 }
 TileShape tile_shape_for(int idx, int prec) { return effective_shape(idx, prec); }

@@ -39,9 +39,9 @@ def _bf16_round(x: np.ndarray) -> np.ndarray:
 # contraction exactness (operand layout, decode, K order, tiling, padding)
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("precision", PRECS)
-@pytest.mark.parametrize("n,m,p", [(300, 70, 40), (2000, 1100, 130)])
-def test_contraction_exact_integers(tgw, precision, n, m, p):
-    say(f"case: exact contraction {precision} n={n} m={m} p={p}")
+@pytest.mark.parametrize("n,m,p,tile", [(300, 70, 40, 0), (2000, 1100, 130, 0), (2000, 1100, 130, 1)])
+def test_contraction_exact_integers(tgw, precision, n, m, p, tile):
+    say(f"case: exact contraction {precision} n={n} m={m} p={p} tile={tile}")
     rng = np.random.default_rng(17 + n)
     codes = rng.integers(0, 3, size=(m, n)).astype(np.uint8)
     codes[5, :] = 1                      # monomorphic: shift = 1 exactly
@@ -50,7 +50,7 @@ def test_contraction_exact_integers(tgw, precision, n, m, p):
     cov = tgw.fit_covariates(None, n_samples=n)
     panel = tgw.prepare_phenotypes(cov, torch.randn(n, p, dtype=torch.float32, device="cuda"), precision)
     panel.debug_set_operand(torch.from_numpy(V).cuda())
-    plan = tgw.Plan([panel])
+    plan = tgw.Plan([panel], tile=tile)
     g = torch.from_numpy(packed).cuda()
     S = plan.debug_contract(g).cpu().numpy().astype(np.float64)
     shift, mean = [x.cpu().numpy() for x in plan.debug_marker_stats(g)]
@@ -163,6 +163,18 @@ def test_cfg1_full(tgw, precision):
     # the causal markers carry real signal
     cm = causal_markers(spec)
     assert np.nanmax(res[0]["nlog10p"][cm]) > 10
+
+
+@pytest.mark.parametrize("precision", ["split", "split16", "split8"])
+def test_cfg1_two_waves_per_simd(tgw, precision):
+    """cfg1 in full on the wide tile with two waves per SIMD (tile 1)."""
+    spec = cohort_spec("cfg1")
+    say(f"case: cfg1 full {precision}, tile 1")
+    codes, packed, C, Y = cohort_arrays(spec, np.arange(spec.n_markers))
+    res, n_tail, _ = gpu_scan(C, [Y], packed, precision, plan_kw={"tile": 1})
+    ref = oracle_scan(codes, C, Y)
+    compare(res[0], ref, ref["df"], f"cfg1 {precision} tile 1 ")
+    assert n_tail == int(np.sum(np.abs(ref["t"]) > 40))
 
 
 @pytest.mark.parametrize("precision", PRECS)
