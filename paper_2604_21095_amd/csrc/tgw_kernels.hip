@@ -1135,16 +1135,19 @@ constexpr int waitcnt_vm_lgkm0(int vm) { return (vm & 15) | ((vm >> 4) << 14) | 
 // vmcnt(vm) only (expcnt and lgkmcnt unconstrained)
 constexpr int waitcnt_vm_only(int vm) { return waitcnt_vm_lgkm0(vm) | (0xF << 8); }
 
-template <int PREC, int MODE, int NW, int WMF>
+template <int PREC, int MODE, int NW, int WMF, int WN = 4>
 __global__ __launch_bounds__(NW * 64) void gemm_wide_kernel(GemmArgs a) {
   static_assert(PREC != kFP32, "the wide kernel runs the split forms");
-  static_assert(NW * WMF == 16 && (WMF == 4 || WMF == 2), "512-marker tiles");
+  static_assert((NW * WMF == 16 && WN == 4 && (WMF == 4 || WMF == 2)) ||
+                    (NW == 4 && WMF == 2 && WN == 8 && PREC == kSplit8),
+                "512 x 128 tiles, or 256 x 256 for the FP8 lo form");
   constexpr bool F8 = PREC == kSplit8;
-  constexpr bool W2 = WMF == 2;  // two waves per SIMD
-  constexpr int WN = 4, NT = NW * 64;
+  constexpr bool W2 = WMF == 2;  // FP8 lo MFMAs by column block: both fragments, WN / 4 blocks per step
+  constexpr int FNS = WN / 4;    // column blocks whose FP8 lo term runs at each step (WMF = 2)
+  constexpr int NT = NW * 64;
   constexpr int TM = NW * WMF * 32;
   constexpr int BB = block_bytes(PREC);
-  constexpr int NSTAGE = F8 ? 4 : 3;
+  constexpr int NSTAGE = F8 ? (WN == 8 ? 3 : 4) : 3;
   constexpr int B_BYTES = WN * BB;  // operand chunk of the column tile
   constexpr int A_BYTES = TM * 16;  // 64 two-bit codes of each marker
   constexpr int STAGE_BYTES = B_BYTES + A_BYTES;
@@ -1337,7 +1340,8 @@ __global__ __launch_bounds__(NW * 64) void gemm_wide_kernel(GemmArgs a) {
           if (j == 0) read_b8(st, B8);  // this chunk's lo fragments, used by all four steps
         }
         if constexpr (F8 && W2) {
-          read_b8_one(st, j, B8[j]);  // column block j's lo fragment, used by this step
+#pragma unroll
+          for (int q = 0; q < FNS; ++q) read_b8_one(st, j * FNS + q, B8[j * FNS + q]);  // used by this step
           if (j == 0) {
 #pragma unroll
             for (int fm = 0; fm < WMF; ++fm) decode8(acur, fm, A8[fm]);  // both fragments, whole chunk
@@ -1379,8 +1383,8 @@ __global__ __launch_bounds__(NW * 64) void gemm_wide_kernel(GemmArgs a) {
         }
         // issue order: copies and LDS reads early, each behind one
         // matrix-core instruction, then the decode, a few VALU ops per MFMA
-        if (F8 && W2) {  // 8 FP16 MFMA; 4 hi + 2 lo fragment reads (+ 2 code rows at step 2)
-          constexpr int NDS = W2 ? WN + 2 : 0;
+        if (F8 && W2) {  // WMF x WN FP16 MFMA; WN hi + 2 FNS lo fragment reads (+ code rows at step 2)
+          constexpr int NDS = W2 ? WN + 2 * FNS : 0;
 #pragma unroll
           for (int q = 0; q < NDS; ++q) {
             __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // DS read
@@ -1451,18 +1455,22 @@ __global__ __launch_bounds__(NW * 64) void gemm_wide_kernel(GemmArgs a) {
         }
         __builtin_amdgcn_sched_barrier(0);
         if constexpr (F8 && W2) {
-          // FP8 lo term of column block j, both fragments, whole chunk
+          // FP8 lo term of column blocks j FNS .. (j + 1) FNS - 1, both fragments, whole chunk
           if (j == 3) dma(ch + NSTAGE, st);  // the stage of chunk ch is free since the barrier
 #pragma unroll
-          for (int fm = 0; fm < WMF; ++fm)
-            acc[fm][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A8[fm], B8[j], acc[fm][j], 0, 0, 0, 127,
-                                                                         0, bscale[j]);
+          for (int q = 0; q < FNS; ++q) {
+            const int fn = j * FNS + q;
+#pragma unroll
+            for (int fm = 0; fm < WMF; ++fm)
+              acc[fm][fn] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A8[fm], B8[fn], acc[fm][fn], 0, 0, 0,
+                                                                            127, 0, bscale[fn]);
+          }
           if (j == 3) {
 #pragma unroll
-            for (int q = 0; q < WMF; ++q) {
-              __builtin_amdgcn_sched_group_barrier(0x010, CHUNK_OPS / WMF, 0);  // VMEM (direct-to-LDS)
-              __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                // MFMA
-              __builtin_amdgcn_sched_group_barrier(0x002, 8, 0);                // VALU
+            for (int q = 0; q < WMF * FNS; ++q) {
+              __builtin_amdgcn_sched_group_barrier(0x010, (CHUNK_OPS + WMF * FNS - 1) / (WMF * FNS), 0);  // VMEM
+              __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                                       // MFMA
+              __builtin_amdgcn_sched_group_barrier(0x002, 8, 0);                                       // VALU
             }
           }
           __builtin_amdgcn_sched_barrier(0);
@@ -1591,10 +1599,11 @@ static const TileShape kShapes[] = {
     {4, 2, 4},  // 3: 256 x 128
     {8, 1, 4},  // 4: 256 x 128, 8 waves
     {8, 2, 2},  // 5: 512 x 64
-    {8, 2, 1},  // 6: 512 x 32 (Q^T g contraction)
+    {4, 2, 8},  // 6: 256 x 256, wide, one wave per SIMD (FP8 lo form; others run shape 0)
+    {8, 2, 1},  // 7: 512 x 32 (Q^T g contraction)
 };
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
-constexpr int kWShape = 6;
+constexpr int kWShape = 7;
 
 int n_tile_shapes() { return kNumShapes - 1; }
 TileShape tile_shape(int idx) { return kShapes[idx]; }
@@ -1604,6 +1613,7 @@ template <int PREC, int MODE>
 static const void* gemm_fn(int idx) {
   if constexpr (PREC == kSplit8) {  // the FP8 lo form exists only as the wide kernel
     if (idx == 1) return (const void*)gemm_wide_kernel<PREC, MODE, 8, 2>;
+    if (idx == 6) return (const void*)gemm_wide_kernel<PREC, MODE, 4, 2, 8>;
     return (const void*)gemm_wide_kernel<PREC, MODE, 4, 4>;
   } else {
     switch (idx) {
@@ -1617,15 +1627,19 @@ static const void* gemm_fn(int idx) {
       case 3: return (const void*)gemm_kernel<PREC, 4, 2, 4, MODE>;
       case 4: return (const void*)gemm_kernel<PREC, 8, 1, 4, MODE>;
       case 5: return (const void*)gemm_kernel<PREC, 8, 2, 2, MODE>;
-      case 6: return (const void*)gemm_kernel<PREC, 8, 2, 1, MODE>;
+      case 6:  // the 256 x 256 wide shape exists for the FP8 lo form only
+        if constexpr (PREC != kFP32) return (const void*)gemm_wide_kernel<PREC, MODE, 4, 4>;
+        return (const void*)gemm_kernel<PREC, 8, 2, 4, MODE>;
+      case 7: return (const void*)gemm_kernel<PREC, 8, 2, 1, MODE>;
     }
     return nullptr;
   }
 }
 
 static TileShape effective_shape(int idx, int prec) {
-  if (prec == kSplit8) return kShapes[idx == 1 ? 1 : 0];
-  if (idx <= 1 && prec == kFP32) return kShapes[2];
+  if (prec == kSplit8) return kShapes[idx == 1 ? 1 : idx == 6 ? 6 : 0];
+  if ((idx <= 1 || idx == 6) && prec == kFP32) return kShapes[2];
+  if (idx == 6) return kShapes[0];
   return kShapes[idx];
 }
 TileShape tile_shape_for(int idx, int prec) { return effective_shape(idx, prec); }

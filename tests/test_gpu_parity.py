@@ -39,7 +39,8 @@ def _bf16_round(x: np.ndarray) -> np.ndarray:
 # contraction exactness (operand layout, decode, K order, tiling, padding)
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("precision", PRECS)
-@pytest.mark.parametrize("n,m,p,tile", [(300, 70, 40, 0), (2000, 1100, 130, 0), (2000, 1100, 130, 1)])
+@pytest.mark.parametrize("n,m,p,tile", [(300, 70, 40, 0), (2000, 1100, 130, 0), (2000, 1100, 130, 1),
+                                        (2000, 1100, 300, 6)])
 def test_contraction_exact_integers(tgw, precision, n, m, p, tile):
     say(f"case: exact contraction {precision} n={n} m={m} p={p} tile={tile}")
     rng = np.random.default_rng(17 + n)
@@ -165,15 +166,16 @@ def test_cfg1_full(tgw, precision):
     assert np.nanmax(res[0]["nlog10p"][cm]) > 10
 
 
-@pytest.mark.parametrize("precision", ["split", "split16", "split8"])
-def test_cfg1_two_waves_per_simd(tgw, precision):
-    """cfg1 in full on the wide tile with two waves per SIMD (tile 1)."""
+@pytest.mark.parametrize("precision,tile", [("split", 1), ("split16", 1), ("split8", 1), ("split8", 6)])
+def test_cfg1_other_wide_shapes(tgw, precision, tile):
+    """cfg1 in full on the wide tiles with two waves per SIMD (tile 1) and,
+    for the FP8 lo form, 256 x 256 with one wave per SIMD (tile 6)."""
     spec = cohort_spec("cfg1")
-    say(f"case: cfg1 full {precision}, tile 1")
+    say(f"case: cfg1 full {precision}, tile {tile}")
     codes, packed, C, Y = cohort_arrays(spec, np.arange(spec.n_markers))
-    res, n_tail, _ = gpu_scan(C, [Y], packed, precision, plan_kw={"tile": 1})
+    res, n_tail, _ = gpu_scan(C, [Y], packed, precision, plan_kw={"tile": tile})
     ref = oracle_scan(codes, C, Y)
-    compare(res[0], ref, ref["df"], f"cfg1 {precision} tile 1 ")
+    compare(res[0], ref, ref["df"], f"cfg1 {precision} tile {tile} ")
     assert n_tail == int(np.sum(np.abs(ref["t"]) > 40))
 
 
