@@ -115,6 +115,61 @@ def cpu_baseline(spec, n_markers: int):
     }
 
 
+def panel_scale_run(args, tgw, torch):
+    """cfg4 (N=23,000, M=1,000,000, P=20,480, K=10) in the headline precision with
+    reduced outputs (per-phenotype best test + hit list): one warm-up step and
+    one timed step, main kernel timed with HIP events."""
+    from synth import cohort_spec, packed_rows_torch, panel_inputs, row_bytes_for
+    spec = cohort_spec("cfg4")
+    N, M = spec.n_samples, spec.n_markers
+    t0 = time.perf_counter()
+    geno = torch.empty((M, row_bytes_for(N)), dtype=torch.uint8, device="cuda")
+    packed_rows_torch(spec, 0, M, "cuda", out=geno, chunk=8192)
+    C, Y = panel_inputs(spec, 0)
+    Cd, Yd = torch.from_numpy(C).cuda(), torch.from_numpy(Y).cuda()
+    del C, Y
+    P = Yd.shape[1]
+    best = tgw.make_best([P])
+    hits, hit_count = tgw.make_hits(1 << 22)
+    log(f"panel scale: inputs generated in {time.perf_counter() - t0:.1f} s: N={N} M={M} P={P}")
+
+    def step(profile):
+        cov = tgw.fit_covariates(Cd)
+        plan = tgw.Plan([tgw.prepare_phenotypes(cov, Yd, args.precision)], tile=args.tile)
+        best[0].zero_()
+        hit_count.zero_()
+        plan.set_hits(hits, hit_count, args.hit_threshold)
+        if profile:
+            plan.profile(True)
+        plan.scan(geno, [{"best": best[0]}])
+        return plan
+
+    if not args.no_autotune and args.tile < 0:
+        p0 = step(False)
+        p0.check()
+        p0.autotune(geno, [{"best": best[0]}], 0, min(M, 131072))
+    step(False).check()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = step(True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    n_tail = plan.check()
+    ms, n = plan.profile_read()
+    ms /= max(1, n)
+    achieved = 2.0 * N * M * P / (ms / 1e3) / 1e12
+    peak = PEAK_FP32_TFLOPS if args.precision == "fp32" else PEAK_BF16_TFLOPS
+    out = {"workload": f"cfg4: N={N} M={M} P={P} K={spec.panels[0].n_cov}, reduced outputs",
+           "value": M * P / dt, "unit": "tests/s", "ms_per_step": dt * 1e3, "main_kernel_ms": ms,
+           "main_kernel_tflops": achieved, "roofline_frac": achieved / peak, "tile": plan.info()["tile"],
+           "hits": int(hit_count.item()), "tail_tests": n_tail}
+    log(f"panel scale: {dt * 1e3:.1f} ms/step, {M * P / dt:.3e} tests/s, main kernel {ms:.1f} ms, "
+        f"{achieved:.1f} TFLOP/s algorithmic, {out['hits']} hits")
+    del geno, Cd, Yd, best, hits, plan
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -127,11 +182,17 @@ def main():
     ap.add_argument("--beside-steps", type=int, default=1)
     ap.add_argument("--markers", type=int, default=0, help="override M (0 = the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-markers", type=int, default=16384)
+    ap.add_argument("--cpu-markers", type=int, default=0, help="0: about 15 s of oracle work (16,384 x 2,048 / P)")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tile", type=int, default=-1)
     ap.add_argument("--out-budget-gb", type=float, default=60.0)
+    ap.add_argument("--outputs", default="dense", choices=["dense", "reduced"],
+                    help="dense: r, beta, se, t, -log10 p for every test (ring of rows); reduced: per-phenotype "
+                         "best test and a hit list at -log10 p >= --hit-threshold, no dense matrices")
+    ap.add_argument("--hit-threshold", type=float, default=7.3)
     ap.add_argument("--copy-calibration", action="store_true", help="run only the 1 GiB copy used to scale counters")
+    ap.add_argument("--no-panel-scale", action="store_true",
+                    help="skip the panel-scale run (cfg4: P=20,480, reduced outputs) reported beside the headline")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
@@ -172,14 +233,27 @@ def main():
     torch.cuda.synchronize()
     log(f"inputs generated in {time.perf_counter() - t0:.1f} s: N={N} M={M} panels={n_panels} P={P} K={K}")
 
-    ring = int(max(1024, min(M, args.out_budget_gb * 1e9 / (P * 20))))
-    outs = tgw.make_outputs(Ps, ring)
+    reduced = args.outputs == "reduced"
+    if reduced:
+        ring = M
+        bests = tgw.make_best(Ps)
+        outs = [{"best": b} for b in bests]
+        hits, hit_count = tgw.make_hits(1 << 22)
+    else:
+        ring = int(max(1024, min(M, args.out_budget_gb * 1e9 / (P * 20))))
+        outs = tgw.make_outputs(Ps, ring)
     stream = torch.cuda.current_stream()
 
     def make_plan(precision, tile):
         covs = [tgw.fit_covariates(c) for c in Cds]
         panels = [tgw.prepare_phenotypes(cv, y, precision) for cv, y in zip(covs, Yds)]
-        return tgw.Plan(panels, tile=tile)
+        plan = tgw.Plan(panels, tile=tile)
+        if reduced:
+            for b in bests:
+                b.zero_()
+            hit_count.zero_()
+            plan.set_hits(hits, hit_count, args.hit_threshold)
+        return plan
 
     def one_step(precision, plan_ref, profile=False):
         plan = make_plan(precision, args.tile)
@@ -242,10 +316,18 @@ def main():
                         "tile": planb.info()["tile"]}
         log(f"{prec}: {dtb * 1e3:.1f} ms/step, {tests / dtb:.3e} tests/s, main kernel {msb:.2f} ms")
 
+    # ---------------------------------------------------------------- panel scale (P = 20,480)
+    panel_scale = None
+    if not args.no_panel_scale and args.workload == "cfg3" and not args.markers:
+        del outs, geno, Cds, Yds
+        plan = planb = None
+        torch.cuda.empty_cache()
+        panel_scale = panel_scale_run(args, tgw, torch)
+
     # ---------------------------------------------------------------- CPU baseline
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(spec, min(args.cpu_markers, M))
+        cpu = cpu_baseline(spec, min(args.cpu_markers or max(256, 16384 * 2048 // P), M))
         log(f"cpu oracle: {cpu['value']:.3e} tests/s on {cpu['cores']} threads ({cpu['seconds']:.1f} s)")
 
     traffic = load_traffic(args.workload, args.precision, info["tile"])
@@ -296,6 +378,10 @@ def main():
         "split16_scan": beside.get("split16"),
         "split8_scan": beside.get("split8"),
         "tail_tests": n_tail,
+        "panel_scale": panel_scale,
+        "outputs": ("dense r, beta, se, t, -log10 p" if not reduced else
+                    f"reduced: per-phenotype best test + hit list at -log10 p >= {args.hit_threshold} "
+                    f"({int(hit_count.item())} hits in the last step)"),
         "context": PAPER_CONTEXT,
     }
     print(json.dumps(line), flush=True)
