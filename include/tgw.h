@@ -118,6 +118,9 @@ typedef struct tgw_graph tgw_graph;           /* a captured tgw_scan call     */
  *            largest -log10 p over every marker scanned into it, packed as
  *            (IEEE bits of that -log10 p) << 32 | (0xffffffff - marker), with
  *            the absolute marker index (the smallest one among equal maxima).
+ *            Within a call the test is chosen by |t|, on which -log10 p at
+ *            the panel's fixed df is increasing; its -log10 p is FP64 for
+ *            |t| > 40.
  *            The caller zeroes it before the first scan; scans merge by
  *            maximum, so marker ranges may be split over calls (markers
  *            < 2^32).  NaN tests never enter; 0 means none.  Independent of
@@ -244,7 +247,8 @@ tgw_status tgw_scan(tgw_plan* plan, const uint8_t* d_geno, int64_t n_markers, in
  * for the following tgw_scan calls on this plan and for graphs captured
  * afterwards: every test with -log10 p >= threshold is appended to d_hits
  * (device, `capacity` entries) at index atomicAdd(d_count, 1), in no
- * particular order.  Entries past `capacity` are dropped but still counted:
+ * particular order; for |t| > 40 the decision is taken on the FP64 value.
+ * Entries past `capacity` are dropped but still counted:
  * *d_count > capacity after a scan means the list is truncated.  The caller
  * owns both buffers and zeroes *d_count; successive scans keep appending.
  * d_hits == NULL turns the list off.  The autotuner never appends. */

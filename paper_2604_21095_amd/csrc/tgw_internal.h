@@ -89,8 +89,8 @@ struct HitDev {
   Hit* entries;               // NULL: no hit list
   unsigned long long* count;
   int64_t capacity;
-  float threshold;
-  int32_t pad;
+  float threshold;            // -log10 p
+  float t_floor;              // |t| below this cannot reach the threshold at any df
 };
 
 // one 32-column block of the virtual concatenation of all panels' columns
@@ -107,7 +107,7 @@ struct TailEntry {
   int32_t panel;
   int32_t col;
   float r;
-  int32_t hit;  // index of the test's entry in the hit list, -1 if none
+  int32_t pad;
 };
 
 struct TailDev {
@@ -119,7 +119,7 @@ struct TailDev {
 struct GemmArgs {
   const uint8_t* geno;
   int64_t row_bytes;
-  int64_t m0;        // absolute index of the block's first marker
+  int64_t m0;        // row of the block's first marker in geno
   int64_t nm;        // markers in the block
   int64_t out_row0;  // output row of the block's first marker
   int32_t n_chunks;

@@ -665,6 +665,19 @@ __device__ inline unsigned long long best_pack(float nl, int64_t marker) {
          (unsigned long long)(0xffffffffu - (uint32_t)marker);
 }
 
+__device__ inline void append_hit(const HitDev& hits, int64_t marker, int j, int64_t p, float nl, float r) {
+  const unsigned long long idx = atomicAdd(hits.count, 1ull);
+  if (idx < (unsigned long long)hits.capacity) {
+    Hit h;
+    h.marker = marker;
+    h.panel = j;
+    h.pheno = (int32_t)p;
+    h.nl = nl;
+    h.r = r;
+    hits.entries[idx] = h;
+  }
+}
+
 __global__ void tail_kernel(TailDev t, const PanelDev* __restrict__ panels, const OutDev* __restrict__ outs,
                             HitDev hits, int64_t m_begin) {
   const unsigned long long cnt = t.count[0];
@@ -680,7 +693,7 @@ __global__ void tail_kernel(TailDev t, const PanelDev* __restrict__ panels, cons
     const OutDev o = outs[e.panel];
     if (o.nl) o.nl[e.row * o.ld + e.col] = nl;
     if (o.best) atomicMax(o.best + e.col, best_pack(nl, m_begin + e.row));  // replaces the lower bound
-    if (e.hit >= 0) hits.entries[e.hit].nl = nl;
+    if (hits.entries && nl >= hits.threshold) append_hit(hits, m_begin + e.row, e.panel, e.col, nl, e.r);
   }
 }
 
@@ -733,9 +746,10 @@ __device__ __forceinline__ f32x16 mfma16(const u32x4& a, const u32x4& b, const f
 
 // -log10 p, t, beta, SE and r of one test; writes the requested outputs,
 // appends the test to the hit list when it reaches the threshold, and
-// returns its -log10 p for the per-column best (NaN when undefined; for
-// |t| > 40 the table's value at 40, a lower bound that the FP64 tail kernel
-// replaces)
+// returns |t| for the per-column best (NaN when undefined).  -log10 p is
+// evaluated only where an output needs it: for the dense matrix, for tests
+// that may reach the hit threshold, and (in FP64, by the tail kernel) for
+// |t| > 40.
 __device__ __forceinline__ float epilogue_one(float S, float invh, float invny, float sp, const PanelDev& pd,
                                               const OutDev& od, int64_t o, int64_t row, int j, int64_t p,
                                               const TailDev& tail, const HitDev& hits, int64_t marker) {
@@ -748,8 +762,10 @@ __device__ __forceinline__ float epilogue_one(float S, float invh, float invny, 
   if (od.beta) gstore(od.beta + o, r * sp * invh);
   if (od.se) gstore(od.se + o, sp * invh * sqrtf(omr2) * pd.inv_sqrt_df);
   if (od.t) gstore(od.t + o, t);
-  if (!(od.nl || od.best || hits.entries)) return __builtin_nanf("");
   const float at = fabsf(t);
+  if (!(od.nl || od.best || hits.entries)) return at;
+  const bool hit_cand = hits.entries && at >= hits.t_floor;
+  if (!od.nl && !hit_cand && at <= kTMax) return at;  // best tracks |t|; no -log10 p needed here
   float nl, track;
   bool to_tail = false;
   if (at <= kTMax) {
@@ -763,20 +779,6 @@ __device__ __forceinline__ float epilogue_one(float S, float invh, float invny, 
     nl = INFINITY;
     to_tail = true;
   }
-  int32_t hit = -1;
-  if (hits.entries && track >= hits.threshold) {
-    const unsigned long long idx = atomicAdd(hits.count, 1ull);
-    if (idx < (unsigned long long)hits.capacity) {
-      Hit h;
-      h.marker = marker;
-      h.panel = j;
-      h.pheno = (int32_t)p;
-      h.nl = to_tail ? track : nl;
-      h.r = r;
-      hits.entries[idx] = h;
-      hit = (int32_t)idx;
-    }
-  }
   if (to_tail) {
     const unsigned long long idx = atomicAdd(tail.count, 1ull);
     if (idx < (unsigned long long)tail.capacity) {
@@ -785,14 +787,16 @@ __device__ __forceinline__ float epilogue_one(float S, float invh, float invny, 
       e.panel = j;
       e.col = (int32_t)p;
       e.r = r;
-      e.hit = hit;
-      tail.entries[idx] = e;
+      e.pad = 0;
+      tail.entries[idx] = e;  // the tail kernel writes -log10 p and decides the hit
     } else {
-      nl = track;  // lower bound
+      nl = track;  // lower bound; the call reports the overflow
+      to_tail = false;
     }
   }
+  if (hit_cand && !to_tail && nl >= hits.threshold) append_hit(hits, marker, j, p, nl, r);
   if (od.nl) gstore(od.nl + o, nl);
-  return track;
+  return at;
 }
 
 // finish one 32-column block of a wave's staged accumulators (stage holds
@@ -809,17 +813,17 @@ __device__ __forceinline__ void finish_block(const float* stage, const GemmArgs&
   const bool colok = r32 < blk.ncol;
   const float invny = colok ? gload<float>(pd.invny + p) : 0.f;
   const float sp = colok ? gload<float>(pd.scale + p) : 0.f;
-  float bv = -1.0f;
+  float bv = -1.0f;  // largest |t| of this lane's rows (-log10 p is increasing in |t| at fixed df)
   int64_t bm = 0;
   for (int rr = h; rr < WMF * 32; rr += 2) {
     const int64_t mr = rowbase + rr;
     if (colok && mr < a.nm) {
       const float invh = gload<float>(a.invh + mr * a.n_panels + j);
       const int64_t row = a.out_row0 + mr;
-      const float nl = epilogue_one(stage[rr * 32 + r32], invh, invny, sp, pd, od, row * od.ld + p, row, j, p,
+      const float at = epilogue_one(stage[rr * 32 + r32], invh, invny, sp, pd, od, row * od.ld + p, row, j, p,
                                     a.tail, a.hits, a.m_begin + row);
-      if (nl > bv) {
-        bv = nl;
+      if (at > bv) {
+        bv = at;
         bm = a.m_begin + row;
       }
     }
@@ -831,7 +835,12 @@ __device__ __forceinline__ void finish_block(const float* stage, const GemmArgs&
       bv = ov;
       bm = om;
     }
-    if (h == 0 && colok && bv >= 0.0f) atomicMax(od.best + p, best_pack(bv, bm));
+    if (h == 0 && colok && bv >= 0.0f) {
+      // beyond |t| = 40 the table's value at 40 is a lower bound that the
+      // FP64 tail kernel replaces
+      const float nl = bv == INFINITY ? INFINITY : table_nlog10p(pd.table, bv <= kTMax ? bv : kTMax);
+      atomicMax(od.best + p, best_pack(nl, bm));
+    }
   }
 }
 

@@ -1,6 +1,6 @@
 // Host runtime behind the C ABI in include/tgw.h: handles, argument checks,
 // workspace, the per-block launch sequence, autotuner and graph capture.
-#include "../../include/tgw.h"
+#include "tgw_host.h"
 #include "tgw_internal.h"
 
 #include <algorithm>
@@ -22,34 +22,15 @@ using namespace tgw;
 // ---------------------------------------------------------------------------
 static thread_local std::string g_err;
 
-static tgw_status fail(tgw_status s, const std::string& msg) {
+tgw_status tgw::fail(tgw_status s, const std::string& msg) {
   g_err = msg;
   return s;
 }
 
-static tgw_status hip_fail(hipError_t e, const char* what) {
+tgw_status tgw::hip_fail(hipError_t e, const char* what) {
   return fail(e == hipErrorOutOfMemory ? TGW_ERR_OUT_OF_MEMORY : TGW_ERR_DEVICE,
               std::string(what) + ": " + hipGetErrorString(e));
 }
-
-#define HIP_TRY(expr)                                   \
-  do {                                                  \
-    hipError_t _e = (expr);                             \
-    if (_e != hipSuccess) return hip_fail(_e, #expr);   \
-  } while (0)
-
-#define TGW_GUARD_BEGIN try {
-#define TGW_GUARD_END                                                  \
-  }                                                                    \
-  catch (const std::bad_alloc&) {                                      \
-    return fail(TGW_ERR_OUT_OF_MEMORY, "host allocation failed");      \
-  }                                                                    \
-  catch (const std::exception& ex) {                                   \
-    return fail(TGW_ERR_DEVICE, std::string("internal error: ") + ex.what()); \
-  }                                                                    \
-  catch (...) {                                                        \
-    return fail(TGW_ERR_DEVICE, "internal error");                     \
-  }
 
 // ---------------------------------------------------------------------------
 // device properties
@@ -552,15 +533,9 @@ extern "C" tgw_status tgw_plan_info(const tgw_plan* pl, int32_t* tile, int32_t* 
 // ---------------------------------------------------------------------------
 // the scan
 // ---------------------------------------------------------------------------
-struct ScanCall {
-  const uint8_t* geno;
-  int64_t n_markers, row_bytes;
-  int code;
-  int64_t m_begin, m_end;
-  const tgw_outputs* outs;
-};
+int64_t tgw::plan_samples(const tgw_plan* pl) { return pl->n; }
 
-static tgw_status check_call(const tgw_plan* pl, const ScanCall& c, bool need_outs) {
+tgw_status tgw::check_call(const tgw_plan* pl, const ScanCall& c, bool need_outs) {
   if (!pl) return fail(TGW_ERR_INVALID_ARG, "plan is NULL");
   if (!c.geno) return fail(TGW_ERR_INVALID_ARG, "d_geno is NULL");
   if (((uintptr_t)c.geno & 15) != 0) return fail(TGW_ERR_SHAPE, "d_geno must be 16-byte aligned");
@@ -585,7 +560,7 @@ static GemmArgs base_args(const tgw_plan* pl, const ScanCall& c, int64_t m0, int
   GemmArgs a{};
   a.geno = c.geno;
   a.row_bytes = c.row_bytes;
-  a.m0 = m0;
+  a.m0 = m0 - c.geno_row0;
   a.nm = nm;
   a.out_row0 = m0 - c.m_begin;
   a.n_chunks = pl->n_chunks;
@@ -608,7 +583,7 @@ static hipError_t enqueue_block_stats(tgw_plan* pl, const ScanCall& c, int64_t m
   StatsArgs sa{};
   sa.geno = c.geno;
   sa.row_bytes = c.row_bytes;
-  sa.m0 = m0;
+  sa.m0 = m0 - c.geno_row0;
   sa.nm = nm;
   sa.n = pl->n;
   sa.code = c.code;
@@ -670,17 +645,31 @@ static hipError_t enqueue_bind(tgw_plan* pl, const tgw_outputs* outs, hipStream_
   return hipSuccess;
 }
 
-static hipError_t enqueue_scan(tgw_plan* pl, const ScanCall& c, hipStream_t s) {
-  hipError_t e = enqueue_bind(pl, c.outs, s);
+hipError_t tgw::enqueue_scan_begin(tgw_plan* pl, const tgw_outputs* outs, hipStream_t s) {
+  hipError_t e = enqueue_bind(pl, outs, s);
   if (e == hipSuccess) e = launch_tail_reset(TailDev{pl->tail_entries, pl->tail_count, pl->tail_cap}, s);
-  for (int64_t m0 = c.m_begin; e == hipSuccess && m0 < c.m_end; m0 += pl->MB) {
-    const int64_t nm = std::min(pl->MB, c.m_end - m0);
+  return e;
+}
+
+hipError_t tgw::enqueue_scan_rows(tgw_plan* pl, const ScanCall& c, int64_t m_lo, int64_t m_hi, hipStream_t s) {
+  hipError_t e = hipSuccess;
+  for (int64_t m0 = m_lo; e == hipSuccess && m0 < m_hi; m0 += pl->MB) {
+    const int64_t nm = std::min(pl->MB, m_hi - m0);
     e = enqueue_block_stats(pl, c, m0, nm, s);
     if (e == hipSuccess) e = enqueue_main(pl, c, m0, nm, pl->tile, s);
   }
-  if (e == hipSuccess)
-    e = launch_tail(TailDev{pl->tail_entries, pl->tail_count, pl->tail_cap}, pl->d_panels, pl->d_outs, pl->hits,
-                    c.m_begin, s);
+  return e;
+}
+
+hipError_t tgw::enqueue_scan_end(tgw_plan* pl, int64_t m_begin, hipStream_t s) {
+  return launch_tail(TailDev{pl->tail_entries, pl->tail_count, pl->tail_cap}, pl->d_panels, pl->d_outs, pl->hits,
+                     m_begin, s);
+}
+
+static hipError_t enqueue_scan(tgw_plan* pl, const ScanCall& c, hipStream_t s) {
+  hipError_t e = enqueue_scan_begin(pl, c.outs, s);
+  if (e == hipSuccess) e = enqueue_scan_rows(pl, c, c.m_begin, c.m_end, s);
+  if (e == hipSuccess) e = enqueue_scan_end(pl, c.m_begin, s);
   return e;
 }
 
@@ -695,7 +684,20 @@ extern "C" tgw_status tgw_plan_set_hits(tgw_plan* pl, tgw_hit* d_hits, int64_t c
   if (capacity < 0) return fail(TGW_ERR_INVALID_ARG, "negative capacity");
   if (!(threshold == threshold)) return fail(TGW_ERR_INVALID_ARG, "threshold is NaN");
   static_assert(sizeof(tgw_hit) == sizeof(Hit), "tgw_hit layout");
-  pl->hits = HitDev{(Hit*)d_hits, d_count, capacity, threshold, 0};
+  // |t| below which -log10 p < threshold at every df: the normal tail is
+  // lighter than Student's t, so -log10(erfc(|t|/sqrt 2)) bounds -log10 p
+  // from above; bisection, then a small safety margin
+  double lo = 0.0, hi = (double)kTMax;
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    const double nl = -std::log10(std::erfc(mid / std::sqrt(2.0)));
+    if (nl < (double)threshold)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  const float t_floor = (float)(lo * (1.0 - 1e-3));
+  pl->hits = HitDev{(Hit*)d_hits, d_count, capacity, threshold, t_floor};
   return TGW_OK;
 }
 
@@ -703,7 +705,7 @@ extern "C" tgw_status tgw_scan(tgw_plan* pl, const uint8_t* d_geno, int64_t n_ma
                                tgw_geno_code code, int64_t m_begin, int64_t m_end, const tgw_outputs* outs,
                                void* stream) {
   TGW_GUARD_BEGIN
-  ScanCall c{d_geno, n_markers, row_bytes, (int)code, m_begin, m_end, outs};
+  ScanCall c{d_geno, n_markers, row_bytes, (int)code, m_begin, m_end, outs, 0};
   tgw_status st = check_call(pl, c, true);
   if (st != TGW_OK) return st;
   if (m_begin == m_end) return TGW_OK;
@@ -729,7 +731,7 @@ extern "C" tgw_status tgw_plan_autotune(tgw_plan* pl, const uint8_t* d_geno, int
                                         tgw_geno_code code, int64_t m_begin, int64_t m_end,
                                         const tgw_outputs* outs, void* stream, double* best_ms) {
   TGW_GUARD_BEGIN
-  ScanCall c{d_geno, n_markers, row_bytes, (int)code, m_begin, m_end, outs};
+  ScanCall c{d_geno, n_markers, row_bytes, (int)code, m_begin, m_end, outs, 0};
   tgw_status st = check_call(pl, c, true);
   if (st != TGW_OK) return st;
   if (m_begin == m_end) return fail(TGW_ERR_SHAPE, "autotune needs at least one marker");
@@ -814,7 +816,7 @@ extern "C" tgw_status tgw_graph_create(tgw_plan* pl, const uint8_t* d_geno, int6
   TGW_GUARD_BEGIN
   if (!out) return fail(TGW_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
-  ScanCall c{d_geno, n_markers, row_bytes, (int)code, m_begin, m_end, outs};
+  ScanCall c{d_geno, n_markers, row_bytes, (int)code, m_begin, m_end, outs, 0};
   tgw_status st = check_call(pl, c, true);
   if (st != TGW_OK) return st;
   hipStream_t s;
@@ -863,7 +865,7 @@ extern "C" tgw_status tgw_debug_contract(tgw_plan* pl, const uint8_t* d_geno, in
                                          tgw_geno_code code, int64_t m_begin, int64_t m_end, float* d_S, int64_t lds,
                                          void* stream) {
   TGW_GUARD_BEGIN
-  ScanCall c{d_geno, n_markers, row_bytes, (int)code, m_begin, m_end, nullptr};
+  ScanCall c{d_geno, n_markers, row_bytes, (int)code, m_begin, m_end, nullptr, 0};
   tgw_status st = check_call(pl, c, false);
   if (st != TGW_OK) return st;
   if (pl->n_panels != 1) return fail(TGW_ERR_INVALID_ARG, "debug contraction needs a one-panel plan");
@@ -901,7 +903,7 @@ extern "C" tgw_status tgw_debug_marker_stats(tgw_plan* pl, const uint8_t* d_geno
                                              int64_t row_bytes, tgw_geno_code code, int64_t m_begin, int64_t m_end,
                                              double* d_shift, double* d_mean, void* stream) {
   TGW_GUARD_BEGIN
-  ScanCall c{d_geno, n_markers, row_bytes, (int)code, m_begin, m_end, nullptr};
+  ScanCall c{d_geno, n_markers, row_bytes, (int)code, m_begin, m_end, nullptr, 0};
   tgw_status st = check_call(pl, c, false);
   if (st != TGW_OK) return st;
   hipStream_t s = (hipStream_t)stream;

@@ -168,3 +168,25 @@ def test_reduced_outputs_batched_panels(tgw):
         nl, marker = tgw.unpack_best(best[j])
         _check_best(nl, marker, ref)
         _check_hits(h, ref, 6.0, panel=j)
+
+
+@pytest.mark.parametrize("precision", ["split8", "fp32"])
+def test_hit_threshold_above_table_range(tgw, precision):
+    """A threshold above -log10 p at |t| = 40 keeps exactly the tail tests that
+    reach it: the decision waits for the FP64 value."""
+    codes, C, Y = _workload()
+    m, n = codes.shape
+    say(f"case: hit threshold 1000, {precision}")
+    ref = oracle_scan(codes, C, Y)
+    thr = 1000.0
+    want = set(zip(*np.nonzero(np.nan_to_num(ref["nlog10p"], nan=-1.0) >= thr)))
+    assert len(want) == 1
+    cov = tgw.fit_covariates(torch.from_numpy(C).cuda())
+    plan = tgw.Plan([tgw.prepare_phenotypes(cov, torch.from_numpy(Y).cuda(), precision)])
+    hits, count = tgw.make_hits(16)
+    plan.set_hits(hits, count, thr)
+    plan.scan(torch.from_numpy(pack_codes_np(codes, row_bytes_for(n))).cuda(), [{}])
+    plan.check()
+    h = tgw.read_hits(hits, count)
+    assert set(zip(h["marker"].tolist(), h["pheno"].tolist())) == want
+    _check_hits(h, ref, thr)
