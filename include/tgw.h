@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define TGW_ABI_VERSION 2
+#define TGW_ABI_VERSION 3
 
 typedef enum {
   TGW_OK = 0,
@@ -277,6 +277,56 @@ tgw_status tgw_graph_create(tgw_plan* plan, const uint8_t* d_geno, int64_t n_mar
                             const tgw_outputs* outs, tgw_graph** out);
 tgw_status tgw_graph_launch(tgw_graph* graph, void* stream);
 void tgw_graph_free(tgw_graph* graph);
+
+/* ---- PLINK 1 binary genotype input ----------------------------------------
+ * The paper's workflow reads PLINK (and BGEN, NumPy) genotype inputs directly
+ * and aligns phenotype and covariate tables to the genotypes by sample ID
+ * (Abstract; Introduction), and notes that end-to-end speed then depends on
+ * the reader and storage bandwidth (Methods 2.4; Discussion).  These calls
+ * read a variant-major .bed file (3 magic bytes 6c 1b 01, then per marker
+ * ceil(n/4) bytes, sample s at bits 2(s & 3) of byte s >> 2, codes 00 / 01 /
+ * 10 / 11 = 0 / missing / 1 / 2 copies of the second allele, i.e.
+ * TGW_CODE_PLINK_BED), and stream it through the scan.  A tgw_bed handle is
+ * not thread-safe: one call at a time. */
+typedef struct tgw_bed tgw_bed;
+
+/* Opens `path` (host) holding n_samples samples (the lines of its .fam).
+ * Errors: TGW_ERR_INVALID_ARG (cannot open / not a variant-major .bed),
+ * TGW_ERR_SHAPE (file size is not 3 + n_markers * ceil(n_samples / 4)).
+ * All samples are selected, in file order. */
+tgw_status tgw_bed_open(const char* path, int64_t n_samples, tgw_bed** out);
+/* Waits for the handle's pending streamed work, frees its buffers, closes. */
+void tgw_bed_close(tgw_bed* bed);
+tgw_status tgw_bed_info(const tgw_bed* bed, int64_t* n_file_samples, int64_t* n_markers, int64_t* n_selected);
+/* Sample selection (host array): scan sample j is file sample idx[j],
+ * 0 <= idx[j] < n_file_samples, all distinct; the caller's phenotype and
+ * covariate rows follow the same order.  idx == NULL selects every sample
+ * in file order. */
+tgw_status tgw_bed_select(tgw_bed* bed, const int64_t* idx, int64_t n);
+/* Host read of markers [m_begin, m_end) with the selection applied: row m -
+ * m_begin of `dst` (host, row_bytes >= ceil(n_selected / 4) bytes per row)
+ * holds scan sample j at bits 2(j & 3) of byte j >> 2, and code 01
+ * (missing) past the last selected sample. */
+tgw_status tgw_bed_read(const tgw_bed* bed, int64_t m_begin, int64_t m_end, uint8_t* dst, int64_t row_bytes);
+/* Sample-ID matching against a PLINK sample table (.fam: whitespace-separated
+ * FID IID ... per line): idx[i] = the line (0-based, blank lines skipped) whose
+ * IID equals ids[i], or -1 if none.  Errors if an id is requested twice or a
+ * requested id occurs on several lines.  n_file_samples receives the number
+ * of sample lines, n_found the number of matched ids (each may be NULL). */
+tgw_status tgw_fam_match(const char* fam_path, const char* const* ids, int64_t n_ids, int64_t* idx,
+                         int64_t* n_file_samples, int64_t* n_found);
+/* tgw_scan over markers [m_begin, m_end) of the file (output row m - m_begin,
+ * as for tgw_scan with TGW_CODE_PLINK_BED), streamed in blocks of
+ * block_markers (0: 65,536) through two pinned host buffers and two device
+ * buffers owned by the handle (made on the first call, kept until close):
+ * n_threads host threads (0: 4) read block k while the device copies and
+ * scans block k - 1; a gather kernel applies the sample selection on the
+ * device.  The plan's n_samples must equal the selection's size.  Returns
+ * when every read and host-to-device copy is done; the scan itself may still
+ * run on `stream` (tgw_plan_check waits for it).  On error the outputs are
+ * undefined. */
+tgw_status tgw_scan_bed(tgw_plan* plan, tgw_bed* bed, int64_t m_begin, int64_t m_end, const tgw_outputs* outs,
+                        int64_t block_markers, int32_t n_threads, void* stream);
 
 /* ---- test hook (exactness of the contraction) -------------------------------
  * Writes the raw FP32 contraction S[m][c] = sum_i a_m(i) * v_c(i) of markers

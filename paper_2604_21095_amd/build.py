@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libtgw.so")
-SOURCES = [os.path.join(HERE, "csrc", "tgw_kernels.hip"), os.path.join(HERE, "csrc", "tgw_runtime.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("tgw_kernels.hip", "tgw_runtime.hip", "tgw_bed.hip")]
 HEADER = os.path.join(ROOT, "include", "tgw.h")
 
 HIPCC_FLAGS = [
@@ -22,6 +22,7 @@ HIPCC_FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall",
     "-Wno-unused-function",
+    "-pthread",
 ]
 
 

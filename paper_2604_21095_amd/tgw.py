@@ -108,6 +108,14 @@ _graph_create = _sig("tgw_graph_create", ctypes.c_int, _vp, _vp, _i64, _i64, cty
                      ctypes.POINTER(Outputs), _pp)
 _graph_launch = _sig("tgw_graph_launch", ctypes.c_int, _vp, _vp)
 _graph_free = _sig("tgw_graph_free", None, _vp)
+_bed_open = _sig("tgw_bed_open", ctypes.c_int, ctypes.c_char_p, _i64, _pp)
+_bed_close = _sig("tgw_bed_close", None, _vp)
+_bed_info = _sig("tgw_bed_info", ctypes.c_int, _vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64))
+_bed_select = _sig("tgw_bed_select", ctypes.c_int, _vp, ctypes.POINTER(_i64), _i64)
+_bed_read = _sig("tgw_bed_read", ctypes.c_int, _vp, _i64, _i64, _vp, _i64)
+_fam_match = _sig("tgw_fam_match", ctypes.c_int, ctypes.c_char_p, ctypes.POINTER(ctypes.c_char_p), _i64,
+                  ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64))
+_scan_bed = _sig("tgw_scan_bed", ctypes.c_int, _vp, _vp, _i64, _i64, ctypes.POINTER(Outputs), _i64, _i32, _vp)
 _dbg_contract = _sig("tgw_debug_contract", ctypes.c_int, _vp, _vp, _i64, _i64, ctypes.c_int, _i64, _i64, _vp, _i64,
                      _vp)
 _dbg_set_operand = _sig("tgw_debug_set_operand", ctypes.c_int, _vp, _vp, _i64, _vp)
@@ -408,6 +416,66 @@ class Plan:
         if getattr(self, "_h", None):
             _free(self._h)
             self._h = None
+
+
+class Bed:
+    """A variant-major PLINK 1 .bed file (tgw_bed_*); host-side calls need no GPU."""
+
+    def __init__(self, path: str, n_samples: int):
+        h = ctypes.c_void_p()
+        _check(_bed_open(os.fsencode(path), n_samples, ctypes.byref(h)), "tgw_bed_open")
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self):
+        a, b, c = _i64(), _i64(), _i64()
+        _check(_bed_info(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)), "tgw_bed_info")
+        return {"n_file_samples": a.value, "n_markers": b.value, "n_selected": c.value}
+
+    def select(self, idx: Optional[Sequence[int]]):
+        if idx is None:
+            _check(_bed_select(self._h, None, 0), "tgw_bed_select")
+            return
+        arr = (_i64 * len(idx))(*[int(i) for i in idx])
+        _check(_bed_select(self._h, arr, len(idx)), "tgw_bed_select")
+
+    def read(self, m_begin: int, m_end: int, row_bytes: int):
+        """Host rows [m_begin, m_end) with the selection applied, as a numpy uint8 array."""
+        import numpy as np
+        out = np.empty((m_end - m_begin, row_bytes), dtype=np.uint8)
+        _check(_bed_read(self._h, m_begin, m_end, out.ctypes.data if out.size else None, row_bytes), "tgw_bed_read")
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _bed_close(self._h)
+            self._h = None
+
+    def __del__(self, _free=_bed_close):  # bound early: module globals are gone at interpreter exit
+        if getattr(self, "_h", None):
+            _free(self._h)
+            self._h = None
+
+
+def fam_match(fam_path: str, ids: Sequence[str]):
+    """File sample of each id (-1 if absent), the table's sample count and the number found."""
+    arr = (ctypes.c_char_p * len(ids))(*[str(i).encode() for i in ids])
+    idx = (_i64 * max(1, len(ids)))()
+    nf, nfound = _i64(), _i64()
+    _check(_fam_match(os.fsencode(fam_path), arr, len(ids), idx, ctypes.byref(nf), ctypes.byref(nfound)),
+           "tgw_fam_match")
+    return [idx[i] for i in range(len(ids))], nf.value, nfound.value
+
+
+def scan_bed(plan: "Plan", bed: Bed, outs, m_begin=0, m_end=None, block_markers=0, n_threads=0, stream=None):
+    """tgw_scan_bed: the scan streamed from a .bed file (output row m - m_begin)."""
+    m_end = bed.info()["n_markers"] if m_end is None else m_end
+    arr = _outs_array(outs, plan.panels, m_end - m_begin)
+    _check(_scan_bed(plan.handle, bed.handle, m_begin, m_end, arr, block_markers, n_threads, _stream(stream)),
+           "tgw_scan_bed")
 
 
 class Graph:

@@ -1,12 +1,14 @@
 """Seeded synthetic cohorts for the association scan.
 
 This package only draws random inputs (genotype codes, covariates and
-phenotype panels) and packs genotype codes into 2-bit rows.  It holds none of
+phenotype panels), packs genotype codes into 2-bit rows and writes them as
+PLINK 1 binary files.  It holds none of
 the scan's arithmetic, so that both the FP64 oracle and the GPU path can take
 their inputs from it without sharing any of the method.
 """
 from .cohort import (  # noqa: F401
     CohortSpec,
+    DOSAGE_TO_PLINK,
     PanelSpec,
     causal_markers,
     SEED,
@@ -21,4 +23,5 @@ from .cohort import (  # noqa: F401
     packed_rows_torch,
     row_bytes_for,
     n_pad_for,
+    write_plink,
 )

@@ -192,6 +192,27 @@ def pack_codes_np(codes: np.ndarray, row_bytes: int) -> np.ndarray:
     return (q[:, :, 0] | (q[:, :, 1] << 2) | (q[:, :, 2] << 4) | (q[:, :, 3] << 6)).astype(np.uint8)
 
 
+# genotype code (0, 1, 2 copies; 3 missing) -> PLINK 1 .bed 2-bit code
+# (00 / 10 / 11 = 0 / 1 / 2 copies of the second allele, 01 missing)
+DOSAGE_TO_PLINK = np.array([0, 2, 3, 1], dtype=np.uint8)
+
+
+def write_plink(prefix: str, codes: np.ndarray, iids: Optional[Sequence[str]] = None) -> None:
+    """Write codes (markers x samples, 0/1/2 copies, 3 missing) as a
+    variant-major PLINK 1 .bed and a .fam with the given IIDs (default
+    S0, S1, ...); FID = IID, parents 0, sex 0, phenotype -9."""
+    m, n = codes.shape
+    raw = pack_codes_np(DOSAGE_TO_PLINK[codes], (n + 3) // 4)
+    with open(prefix + ".bed", "wb") as f:
+        f.write(bytes([0x6C, 0x1B, 0x01]))
+        f.write(np.ascontiguousarray(raw).tobytes())
+    ids = [f"S{i}" for i in range(n)] if iids is None else list(iids)
+    assert len(ids) == n
+    with open(prefix + ".fam", "w") as f:
+        for i in ids:
+            f.write(f"{i} {i} 0 0 0 -9\n")
+
+
 def packed_rows_np(spec: CohortSpec, m0: int, m1: int, row_bytes: Optional[int] = None) -> np.ndarray:
     rb = row_bytes_for(spec.n_samples) if row_bytes is None else row_bytes
     codes = geno_codes_np(spec, np.arange(m0, m1))
