@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define TGW_ABI_VERSION 3
+#define TGW_ABI_VERSION 4
 
 typedef enum {
   TGW_OK = 0,
@@ -86,12 +86,18 @@ typedef enum {
   TGW_PREC_SPLIT_F8 = 3
 } tgw_precision;
 
-/* Meaning of the 2-bit genotype codes (sample i of a row sits at bits
- * 2*(i & 3) of byte i >> 2, as in PLINK .bed rows).
+/* Genotype row formats.  The 2-bit codes put sample i of a row at bits
+ * 2*(i & 3) of byte i >> 2, as in PLINK .bed rows:
  *  TGW_CODE_DOSAGE    : 0, 1, 2 = copies of the counted allele, 3 = missing.
  *  TGW_CODE_PLINK_BED : 0 -> 0, 1 -> missing, 2 -> 1, 3 -> 2 (copies of the
- *                       second allele). */
-typedef enum { TGW_CODE_DOSAGE = 0, TGW_CODE_PLINK_BED = 1 } tgw_geno_code;
+ *                       second allele).
+ *  TGW_CODE_DOSAGE8   : one byte per sample (sample i at byte i): q = 0..254
+ *                       is the expected allele count q / 127 (the imputed
+ *                       dosages that the paper's BGEN input carries; Abstract,
+ *                       Introduction), 255 = missing.  Runs in TGW_PREC_FP32
+ *                       and TGW_PREC_SPLIT_F16 (other precisions give
+ *                       TGW_ERR_UNSUPPORTED); beta and SE are per unit dosage. */
+typedef enum { TGW_CODE_DOSAGE = 0, TGW_CODE_PLINK_BED = 1, TGW_CODE_DOSAGE8 = 2 } tgw_geno_code;
 
 typedef struct tgw_covariates tgw_covariates; /* Q of one covariate matrix   */
 typedef struct tgw_panel tgw_panel;           /* one prepared phenotype panel */
@@ -218,16 +224,20 @@ tgw_status tgw_plan_autotune(tgw_plan* plan, const uint8_t* d_geno, int64_t n_ma
 /* ---- the scan (paper Methods 2.2, Eq. 2-3 and the p-value conversion) ----
  * Streams markers [m_begin, m_end) of the packed genotype matrix through
  * every panel of the plan and writes each panel's outputs.
- *   d_geno     device, n_markers rows of row_bytes bytes (2-bit codes, see
- *              tgw_geno_code); 16-byte aligned, row_bytes a multiple of 16 and
- *              >= 16 * ceil(n_samples / 64).  Bytes past sample n_samples-1
- *              are ignored.
+ *   d_geno     device, n_markers rows of row_bytes bytes (see tgw_geno_code);
+ *              16-byte aligned, row_bytes a multiple of 16 and >= 16 *
+ *              ceil(n_samples / 64) for 2-bit codes, >= 64 * ceil(n_samples /
+ *              64) for 8-bit dosages.  Bytes past sample n_samples-1 are
+ *              ignored.
  *   outs       n_panels entries, in the plan's panel order (see tgw_outputs).
  * Per marker: exact integer counts give the mean mu; each call g is fed to
  * the matrix cores as g - c with c = round(64 mu)/64 (exact in BF16 and FP32),
  * a missing call as mu - c rounded to the operand type (error <= 2^-16 in
  * BF16, 2^-21 in FP16); the intercept of the covariate projection removes c
- * exactly.
+ * exactly.  8-bit dosages enter as q - c with the integer c = round(mu) in
+ * units of 1/127 (exact in FP16 and FP32), a missing one as mu - c (error <=
+ * 2^-12 / 127 in FP16).  They run the register-staged tile shapes; the
+ * autotuner keeps a separate choice for them.
  * Results are deterministic run to run.  A scan split into several marker
  * ranges gives bitwise the same outputs as one call when every boundary is a
  * multiple of 512 markers from m_begin (any boundary for FP32 and the 16-bit

@@ -14,7 +14,7 @@ Pinned by the CPU test suite against things other than itself:
   * uniform p-values under simulated null cohorts,
   * invariances (allele flip, phenotype affine maps, sample permutation,
     basis choice),
-  * brute-force decoding of random 2-bit rows.
+  * brute-force decoding of random 2-bit rows and 8-bit dosage rows.
 
 Readings of points the paper leaves open (degrees of freedom, divisor of the
 standardization, missing genotypes, sidedness of p) are listed in the
@@ -22,7 +22,9 @@ module docstrings.
 """
 from .assoc import (  # noqa: F401
     CODE_DOSAGE,
+    CODE_DOSAGE8,
     CODE_PLINK_BED,
+    DOSAGE8_UNIT,
     MARKER_TOL,
     NonFinite,
     PHENO_TOL,
@@ -30,6 +32,7 @@ from .assoc import (  # noqa: F401
     RankDeficient,
     covariate_basis,
     decode,
+    decode_dosage8,
     impute_mean,
     prepare_panel,
     residual_df,

@@ -29,6 +29,8 @@ from .pvalue import nlog10p_two_sided
 
 CODE_DOSAGE = 0
 CODE_PLINK_BED = 1
+CODE_DOSAGE8 = 2  # one byte per sample: q / 127 copies for q <= 254, 255 missing
+DOSAGE8_UNIT = 127.0
 
 # value of each 2-bit code under each coding scheme; NaN = missing call
 _LUT = {
@@ -63,6 +65,20 @@ def decode(packed: np.ndarray, n_samples: int, code: int = CODE_DOSAGE) -> np.nd
         codes[:, :, k] = (packed >> (2 * k)) & 3
     codes = codes.reshape(m, nb * 4)[:, :n_samples]
     return _LUT[code][codes]
+
+
+def decode_dosage8(rows: np.ndarray, n_samples: int) -> np.ndarray:
+    """8-bit dosage rows (sample i at byte i): q / 127 expected copies for
+    q = 0..254, NaN for 255.  The paper's BGEN input carries such imputed
+    dosages (Abstract, Introduction); the byte format is the library's.
+
+    Returns (M, n_samples) float64.
+    """
+    rows = np.asarray(rows, dtype=np.uint8)
+    if rows.shape[1] < n_samples:
+        raise ValueError("row too short for n_samples")
+    q = rows[:, :n_samples].astype(np.float64)
+    return np.where(q == 255.0, np.nan, q / DOSAGE8_UNIT)
 
 
 def impute_mean(G: np.ndarray):
@@ -141,11 +157,10 @@ def scan(G: np.ndarray, C: np.ndarray, Y: np.ndarray, Q: np.ndarray = None):
     G = np.asarray(G, dtype=np.float64)
     G_imp, n_obs, mu = impute_mean(G)
     obs = ~np.isnan(G)
-    # exact integer degeneracy test on observed calls (values are 0/1/2)
-    gi = np.where(obs, G, 0.0).astype(np.int64)
-    sg = gi.sum(axis=1)
-    sg2 = (gi * gi).sum(axis=1)
-    mono = (n_obs * sg2 - sg * sg) == 0
+    # monomorphic: every observed value equal (exact for any value set)
+    gmax = np.where(obs, G, -np.inf).max(axis=1)
+    gmin = np.where(obs, G, np.inf).min(axis=1)
+    mono = gmax == gmin
     G_c = G_imp - G_imp.mean(axis=1, keepdims=True)
     gc2 = np.einsum("ij,ij->i", G_c, G_c)
     G_res = G_imp - (G_imp @ Q) @ Q.T
@@ -170,5 +185,7 @@ def scan(G: np.ndarray, C: np.ndarray, Y: np.ndarray, Q: np.ndarray = None):
 
 def scan_packed(packed: np.ndarray, n_samples: int, C: np.ndarray, Y: np.ndarray,
                 code: int = CODE_DOSAGE):
-    """scan() on 2-bit packed rows."""
+    """scan() on 2-bit packed rows, or on 8-bit dosage rows (CODE_DOSAGE8)."""
+    if code == CODE_DOSAGE8:
+        return scan(decode_dosage8(packed, n_samples), C, Y)
     return scan(decode(packed, n_samples, code), C, Y)

@@ -37,6 +37,8 @@ constexpr int kNumPrec = 4;
 // the FP16 forms store 2^12 y (and 2^12 q_k) so that unit-norm columns stay
 // in FP16's normal range; statistics are invariant to the scale
 constexpr float kF16Scale = 4096.0f;
+// 8-bit dosage q in 0..254 stands for q / 127 copies (255 = missing)
+constexpr float kDosage8Unit = 127.0f;
 __host__ __device__ constexpr int block_bytes(int prec) { return prec == kSplit8 ? kBlockBytes8 : kBlockBytes; }
 // precision of the Q^T g contraction (the FP8 form has no covariate operand
 // of its own: Q^T g runs on the FP16 split)
@@ -47,7 +49,7 @@ enum Mode { kRaw = 0, kTest = 1 };
 // per-marker statistics of one marker block
 struct MarkerStat {
   double gc2;    // ||g_c||^2 of the mean-imputed marker (exact from integer counts)
-  float dmu;     // mu - c, c = mu rounded to 1/64 (BF16) or 1/512 (FP16 forms)
+  float dmu;     // mu - c, c = mu rounded to 1/64 (BF16) or 1/512 (FP16 forms); 8-bit dosages: to an integer
   int32_t flags; // 1 = degenerate (no observed call or monomorphic)
   double mu;
   double shift;  // c
@@ -127,11 +129,12 @@ struct GemmArgs {
   int32_t n_mtiles;
   int32_t n_ctiles;
   int32_t n_panels;
-  int32_t pad0;
+  float gunit;           // operand units per genotype unit (1; 127 for 8-bit dosages): scales beta and SE
   const ColBlock* cblocks;
   const PanelDev* panels;
   const OutDev* outs;
-  const uint4* mlut;     // [nm] decode table of each marker (16-bit: x lo bytes, y hi bytes; z FP8 bytes)
+  const uint4* mlut;     // [nm] decode table of each marker (2-bit codes, 16-bit forms: x lo bytes, y hi
+                         // bytes, z FP8 bytes; FP32: the four values; 8-bit dosages: see kG8Lut)
   const float* wws;      // [nm][n_panels][32]
   const float* invh;     // [nm][n_panels]
   float* raw_out;        // RAW mode destination
@@ -190,11 +193,15 @@ struct TileShape {
 };
 int n_tile_shapes();
 TileShape tile_shape(int idx);
-TileShape tile_shape_for(int idx, int prec);  // the shape a precision actually runs
+// g8: the genotype rows hold 8-bit dosages (one byte per sample), which the
+// register-staged kernel decodes; the wide shapes run shape 2 for them
+TileShape tile_shape_for(int idx, int prec, bool g8 = false);  // the shape a precision actually runs
 // largest resident grid for a tile shape (occupancy x CUs), rounded to 8 XCDs
-int gemm_grid(int idx, int prec, int mode, int n_cu);
-int tile_alias(int idx, int prec);  // smallest tile index that runs the same kernel
-hipError_t launch_gemm(int idx, int prec, int mode, const GemmArgs& a, int grid, hipStream_t s);
+int gemm_grid(int idx, int prec, int mode, int n_cu, bool g8 = false);
+int tile_alias(int idx, int prec, bool g8 = false);  // smallest tile index that runs the same kernel
+hipError_t launch_gemm(int idx, int prec, int mode, const GemmArgs& a, int grid, hipStream_t s, bool g8 = false);
+// precisions that 8-bit dosages run in (exact re-centred operand: FP32 and the FP16 split)
+__host__ __device__ constexpr bool g8_supported(int prec) { return prec == kFP32 || prec == kSplit16; }
 int wgemm_tile();  // tile shape used for the Q^T g contraction
 
 }  // namespace tgw

@@ -20,6 +20,7 @@ namespace tgw {
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 
 // ---------------------------------------------------------------------------
 // small helpers
@@ -539,6 +540,59 @@ __global__ void set_operand_kernel(const float* __restrict__ V, int64_t ldv, int
   }
 }
 
+// 0xff in every byte of d that is 0xff (the 8-bit dosage missing code), 0
+// elsewhere: bit 7 of ((d & 0x7f) + 1) & d is set exactly for 0xff bytes
+// (no carry leaves a byte); 2t - (t >> 7) spreads each marked bit over its byte
+__device__ __forceinline__ uint32_t ff_bytes(uint32_t d) {
+  const uint32_t t = ((d & 0x7f7f7f7fu) + 0x01010101u) & d & 0x80808080u;
+  return (t << 1) - (t >> 7);
+}
+
+// Decode table of a marker of 8-bit dosages (q = 0..254, 255 missing),
+// operand value q - c with an integer c = rint(mu), missing -> mu - c:
+//   x = FP16 pair of -(1024 + c)    (1024 + q is built exactly by byte insertion)
+//   y = FP16 pair of mu - c
+//   z = FP32 bits of c, w = FP32 bits of mu - c   (the FP32 form)
+__device__ void stats_dosage8(const StatsArgs& a, int64_t m, int lane) {
+  const uint32_t* row = (const uint32_t*)(a.geno + (a.m0 + m) * a.row_bytes);
+  const int64_t nd = (a.n + 3) / 4;
+  uint32_t nmiss = 0;
+  uint64_t S1 = 0, S2 = 0;
+  for (int64_t d = lane; d < nd; d += 64) {
+    const uint32_t w = row[d];
+    const int64_t nv = a.n - 4 * d;
+    const uint32_t vm = nv >= 4 ? 0xffffffffu : ((1u << (8 * nv)) - 1u);
+    const uint32_t miss = ff_bytes(w) & vm;
+    const uint32_t obs = w & ~miss & vm;
+    nmiss += __popc(miss) >> 3;
+    S1 += __builtin_amdgcn_udot4(obs, 0x01010101u, 0u, false);
+    S2 += __builtin_amdgcn_udot4(obs, obs, 0u, false);
+  }
+  uint64_t M = nmiss;
+  for (int o = 32; o > 0; o >>= 1) {
+    M += __shfl_xor(M, o);
+    S1 += __shfl_xor(S1, o);
+    S2 += __shfl_xor(S2, o);
+  }
+  if (lane != 0) return;
+  const int64_t n_obs = a.n - (int64_t)M;
+  const int64_t sg = (int64_t)S1, sg2 = (int64_t)S2;
+  const __int128 num128 = (__int128)n_obs * sg2 - (__int128)sg * sg;  // n_obs * sum (q - mu)^2
+  const bool ok = n_obs > 0 && num128 != 0;
+  MarkerStat st;
+  st.flags = ok ? 0 : 1;
+  const double mu = n_obs > 0 ? (double)sg / (double)n_obs : 0.0;
+  const double c = ok ? rint(mu) : 0.0;
+  st.mu = mu;
+  st.shift = c;
+  st.gc2 = n_obs > 0 ? (double)num128 / (double)n_obs : 0.0;
+  st.dmu = (float)(mu - c);
+  const uint32_t nc = f16_bits_rn((float)(-1024.0 - c));
+  const uint32_t dm = f16_bits_rn((float)(mu - c));
+  a.mlut[m] = make_uint4(nc | (nc << 16), dm | (dm << 16), __float_as_uint((float)c), __float_as_uint((float)(mu - c)));
+  a.mstat[m] = st;
+}
+
 // ---------------------------------------------------------------------------
 // per-marker statistics (one wave per marker)
 // ---------------------------------------------------------------------------
@@ -546,6 +600,10 @@ __global__ __launch_bounds__(256) void stats_kernel(StatsArgs a) {
   const int lane = threadIdx.x & 63;
   const int64_t m = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (m >= a.nm) return;
+  if (a.code == 2) {
+    stats_dosage8(a, m, lane);
+    return;
+  }
   const uint32_t* row = (const uint32_t*)(a.geno + (a.m0 + m) * a.row_bytes);
   const int64_t nd = (a.n + 15) / 16;
   int nmiss = 0, c1 = 0, c2 = 0;
@@ -812,7 +870,7 @@ __device__ __forceinline__ void finish_block(const float* stage, const GemmArgs&
   const int64_t p = blk.col0 + r32;
   const bool colok = r32 < blk.ncol;
   const float invny = colok ? gload<float>(pd.invny + p) : 0.f;
-  const float sp = colok ? gload<float>(pd.scale + p) : 0.f;
+  const float sp = colok ? gload<float>(pd.scale + p) * a.gunit : 0.f;  // beta and SE per genotype unit
   float bv = -1.0f;  // largest |t| of this lane's rows (-log10 p is increasing in |t| at fixed df)
   int64_t bm = 0;
   for (int rr = h; rr < WMF * 32; rr += 2) {
@@ -857,8 +915,14 @@ __device__ __forceinline__ void finish_block(const float* stage, const GemmArgs&
 // are dispatched round-robin to XCDs), so that the workgroups of an XCD
 // share column tiles in their L2.
 // ---------------------------------------------------------------------------
-template <int PREC, int NW, int WMF, int WN, int MODE>
+//
+// G8: the rows hold 8-bit dosages, one byte per sample; each lane half reads
+// its 32 bytes of the chunk and builds FP16 q - c by inserting the byte under
+// the exponent of 1024 and subtracting 1024 + c (exact for integers below
+// 2048), or FP32 q - c; a missing byte takes the marker's mu - c.
+template <int PREC, int NW, int WMF, int WN, int MODE, bool G8 = false>
 __global__ __launch_bounds__(NW * 64) void gemm_kernel(GemmArgs a) {
+  static_assert(!G8 || g8_supported(PREC), "8-bit dosages run the FP32 and FP16 split forms");
   constexpr int NT = NW * 64;
   constexpr int TM = NW * WMF * 32;
   constexpr int TILE_BYTES = WN * kBlockBytes;
@@ -902,7 +966,7 @@ __global__ __launch_bounds__(NW * 64) void gemm_kernel(GemmArgs a) {
     for (int fm = 0; fm < WMF; ++fm) {
       int64_t mr = rowbase + fm * 32 + r32;
       mr = mr < a.nm ? mr : a.nm - 1;
-      ap[fm] = a.geno + (a.m0 + mr) * a.row_bytes + 8 * h;
+      ap[fm] = a.geno + (a.m0 + mr) * a.row_bytes + (G8 ? 32 : 8) * h;
       lut[fm] = gload<uint4>(a.mlut + mr);
     }
 
@@ -915,7 +979,11 @@ __global__ __launch_bounds__(NW * 64) void gemm_kernel(GemmArgs a) {
         for (int i = 0; i < 16; ++i) acc[fm][fn][i] = 0.0f;
 
     u32x4 breg[WN][RPB];
-    uint2 areg[WMF], anext[WMF];
+    // this lane's genotype bytes of the chunk: 8 (2-bit codes) or 32 (dosages)
+    struct ARow {
+      u32x4 q[G8 ? 2 : 1];
+    };
+    ARow areg[WMF], anext[WMF];
     auto load_b = [&](int ch) {
 #pragma unroll
       for (int fn = 0; fn < WN; ++fn)
@@ -929,10 +997,21 @@ __global__ __launch_bounds__(NW * 64) void gemm_kernel(GemmArgs a) {
 #pragma unroll
         for (int q = 0; q < RPB; ++q) *(u32x4*)(smem + buf * TILE_BYTES + fn * kBlockBytes + (q * NT + tid) * 16) = breg[fn][q];
     };
-    auto load_a = [&](int ch, uint2* dst) {
+    auto load_a = [&](int ch, ARow* dst) {
 #pragma unroll
-      for (int fm = 0; fm < WMF; ++fm) dst[fm] = gload<uint2>(ap[fm] + (int64_t)ch * 16);
+      for (int fm = 0; fm < WMF; ++fm) {
+        if constexpr (G8) {
+          dst[fm].q[0] = gload<u32x4>(ap[fm] + (int64_t)ch * 64);
+          dst[fm].q[1] = gload<u32x4>(ap[fm] + (int64_t)ch * 64 + 16);
+        } else {
+          const uint2 v = gload<uint2>(ap[fm] + (int64_t)ch * 16);
+          dst[fm].q[0][0] = v.x;
+          dst[fm].q[0][1] = v.y;
+        }
+      }
     };
+    // dword k (4 samples) of this lane's dosage bytes
+    auto dword8 = [&](const ARow& r, int k) -> uint32_t { return k < 4 ? r.q[0][k] : r.q[G8 ? 1 : 0][k & 3]; };
 
     load_b(0);
     load_a(0, areg);
@@ -960,13 +1039,29 @@ __global__ __launch_bounds__(NW * 64) void gemm_kernel(GemmArgs a) {
           u32x4 A[WMF];
 #pragma unroll
           for (int fm = 0; fm < WMF; ++fm) {
-            const uint32_t src = (j < 2) ? areg[fm].x : areg[fm].y;
+            if constexpr (G8) {
+              // slots (2d, 2d+1) of step j take samples 16 (j >> 1) + 4 (j & 1) + d
+              // and that + 8 of this lane half: byte d of dwords k0 and k0 + 2
+              const int k0 = 4 * (j >> 1) + (j & 1);
+              const uint32_t D0 = dword8(areg[fm], k0), D1 = dword8(areg[fm], k0 + 2);
+              const uint32_t M0 = ff_bytes(D0), M1 = ff_bytes(D1);
 #pragma unroll
-            for (int d = 0; d < 4; ++d) {
-              const int t = 4 * (j & 1) + d;
-              const uint32_t R = (src >> (2 * t)) & 0x00030003u;
-              const uint32_t sel = R * 0x101u + 0x04000400u;
-              A[fm][d] = __builtin_amdgcn_perm(lut[fm].y, lut[fm].x, sel);
+              for (int d = 0; d < 4; ++d) {
+                const uint32_t x = __builtin_amdgcn_perm(D1, D0, 0x0c000c00u | ((4u + d) << 16) | d) | 0x64006400u;
+                const uint32_t v = __builtin_bit_cast(uint32_t, __builtin_bit_cast(f16x2, x) +
+                                                                    __builtin_bit_cast(f16x2, lut[fm].x));
+                const uint32_t mk = __builtin_amdgcn_perm(M1, M0, d | (d << 8) | ((4u + d) << 16) | ((4u + d) << 24));
+                A[fm][d] = (mk & lut[fm].y) | (~mk & v);
+              }
+            } else {
+              const uint32_t src = (j < 2) ? areg[fm].q[0][0] : areg[fm].q[0][1];
+#pragma unroll
+              for (int d = 0; d < 4; ++d) {
+                const int t = 4 * (j & 1) + d;
+                const uint32_t R = (src >> (2 * t)) & 0x00030003u;
+                const uint32_t sel = R * 0x101u + 0x04000400u;
+                A[fm][d] = __builtin_amdgcn_perm(lut[fm].y, lut[fm].x, sel);
+              }
             }
           }
           u32x4 nh[WN], nl[WN];
@@ -996,7 +1091,7 @@ __global__ __launch_bounds__(NW * 64) void gemm_kernel(GemmArgs a) {
       } else {
         uint64_t bits[WMF];
 #pragma unroll
-        for (int fm = 0; fm < WMF; ++fm) bits[fm] = (uint64_t)areg[fm].x | ((uint64_t)areg[fm].y << 32);
+        for (int fm = 0; fm < WMF; ++fm) bits[fm] = (uint64_t)areg[fm].q[0][0] | ((uint64_t)areg[fm].q[0][1] << 32);
 #pragma unroll
         for (int j4 = 0; j4 < 8; ++j4) {
           float4 bv[WN];
@@ -1009,10 +1104,15 @@ __global__ __launch_bounds__(NW * 64) void gemm_kernel(GemmArgs a) {
             float av[WMF];
 #pragma unroll
             for (int fm = 0; fm < WMF; ++fm) {
-              const uint32_t c = (uint32_t)(bits[fm] >> (2 * j)) & 3u;
-              const uint32_t lo = (c & 1u) ? lut[fm].y : lut[fm].x;
-              const uint32_t hi = (c & 1u) ? lut[fm].w : lut[fm].z;
-              av[fm] = __uint_as_float((c & 2u) ? hi : lo);
+              if constexpr (G8) {  // sample 32 h + j: byte j of this lane half's 32
+                const uint32_t q = (dword8(areg[fm], j >> 2) >> (8 * (j & 3))) & 0xffu;
+                av[fm] = q == 0xffu ? __uint_as_float(lut[fm].w) : (float)q - __uint_as_float(lut[fm].z);
+              } else {
+                const uint32_t c = (uint32_t)(bits[fm] >> (2 * j)) & 3u;
+                const uint32_t lo = (c & 1u) ? lut[fm].y : lut[fm].x;
+                const uint32_t hi = (c & 1u) ? lut[fm].w : lut[fm].z;
+                av[fm] = __uint_as_float((c & 2u) ? hi : lo);
+              }
             }
 #pragma unroll
             for (int fn = 0; fn < WN; ++fn) {
@@ -1619,6 +1719,20 @@ TileShape tile_shape(int idx) { return kShapes[idx]; }
 int wgemm_tile() { return kWShape; }
 
 template <int PREC, int MODE>
+static const void* gemm_fn_g8(int idx) {  // 8-bit dosages: register-staged shapes only
+  if constexpr (g8_supported(PREC)) {
+    switch (idx) {
+      case 3: return (const void*)gemm_kernel<PREC, 4, 2, 4, MODE, true>;
+      case 4: return (const void*)gemm_kernel<PREC, 8, 1, 4, MODE, true>;
+      case 5: return (const void*)gemm_kernel<PREC, 8, 2, 2, MODE, true>;
+      case 7: return (const void*)gemm_kernel<PREC, 8, 2, 1, MODE, true>;
+      default: return (const void*)gemm_kernel<PREC, 8, 2, 4, MODE, true>;
+    }
+  }
+  return nullptr;
+}
+
+template <int PREC, int MODE>
 static const void* gemm_fn(int idx) {
   if constexpr (PREC == kSplit8) {  // the FP8 lo form exists only as the wide kernel
     if (idx == 1) return (const void*)gemm_wide_kernel<PREC, MODE, 8, 2>;
@@ -1645,42 +1759,49 @@ static const void* gemm_fn(int idx) {
   }
 }
 
-static TileShape effective_shape(int idx, int prec) {
+static TileShape effective_shape(int idx, int prec, bool g8 = false) {
+  if (g8) return kShapes[(idx <= 1 || idx == 6) ? 2 : idx];
   if (prec == kSplit8) return kShapes[idx == 1 ? 1 : idx == 6 ? 6 : 0];
   if ((idx <= 1 || idx == 6) && prec == kFP32) return kShapes[2];
   if (idx == 6) return kShapes[0];
   return kShapes[idx];
 }
-TileShape tile_shape_for(int idx, int prec) { return effective_shape(idx, prec); }
+TileShape tile_shape_for(int idx, int prec, bool g8) { return effective_shape(idx, prec, g8); }
 
-static const void* gemm_fn_any(int idx, int prec, int mode) {
+static const void* gemm_fn_any(int idx, int prec, int mode, bool g8 = false) {
+  if (g8) {
+    if (prec == kSplit16) return mode == kRaw ? gemm_fn_g8<kSplit16, kRaw>(idx) : gemm_fn_g8<kSplit16, kTest>(idx);
+    if (prec == kFP32) return mode == kRaw ? gemm_fn_g8<kFP32, kRaw>(idx) : gemm_fn_g8<kFP32, kTest>(idx);
+    return nullptr;
+  }
   if (prec == kSplit) return mode == kRaw ? gemm_fn<kSplit, kRaw>(idx) : gemm_fn<kSplit, kTest>(idx);
   if (prec == kSplit16) return mode == kRaw ? gemm_fn<kSplit16, kRaw>(idx) : gemm_fn<kSplit16, kTest>(idx);
   if (prec == kSplit8) return mode == kRaw ? gemm_fn<kSplit8, kRaw>(idx) : gemm_fn<kSplit8, kTest>(idx);
   return mode == kRaw ? gemm_fn<kFP32, kRaw>(idx) : gemm_fn<kFP32, kTest>(idx);
 }
 
-int tile_alias(int idx, int prec) {
-  const void* fn = gemm_fn_any(idx, prec, kTest);
+int tile_alias(int idx, int prec, bool g8) {
+  const void* fn = gemm_fn_any(idx, prec, kTest, g8);
   for (int i = 0; i < idx; ++i)
-    if (gemm_fn_any(i, prec, kTest) == fn) return i;
+    if (gemm_fn_any(i, prec, kTest, g8) == fn) return i;
   return idx;
 }
 
-int gemm_grid(int idx, int prec, int mode, int n_cu) {
-  const void* fn = gemm_fn_any(idx, prec, mode);
+int gemm_grid(int idx, int prec, int mode, int n_cu, bool g8) {
+  const void* fn = gemm_fn_any(idx, prec, mode, g8);
+  if (!fn) return 8;
   int occ = 0;
-  const int threads = effective_shape(idx, prec).waves * 64;
+  const int threads = effective_shape(idx, prec, g8).waves * 64;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, threads, 0) != hipSuccess || occ < 1) occ = 1;
   int g = occ * n_cu;
   g = (g / 8) * 8;
   return g < 8 ? 8 : g;
 }
 
-hipError_t launch_gemm(int idx, int prec, int mode, const GemmArgs& a, int grid, hipStream_t s) {
-  const void* fn = gemm_fn_any(idx, prec, mode);
+hipError_t launch_gemm(int idx, int prec, int mode, const GemmArgs& a, int grid, hipStream_t s, bool g8) {
+  const void* fn = gemm_fn_any(idx, prec, mode, g8);
   if (!fn) return hipErrorInvalidValue;
-  const int threads = effective_shape(idx, prec).waves * 64;
+  const int threads = effective_shape(idx, prec, g8).waves * 64;
   GemmArgs arg = a;
   void* params[] = {&arg};
   return hipLaunchKernel(fn, dim3(grid), dim3(threads), params, 0, s);

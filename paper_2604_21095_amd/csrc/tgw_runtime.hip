@@ -120,6 +120,10 @@ struct tgw_plan {
   int tile = 0;
   std::vector<int> grid_main;  // per tile shape
   int grid_w = 0;
+  // 8-bit dosage rows (the FP32 and FP16 split forms): own tile choice and grids
+  int tile8 = 2;
+  std::vector<int> grid_main8;
+  int grid_w8 = 0;
   bool profile = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
 };
@@ -510,8 +514,18 @@ extern "C" tgw_status tgw_plan_create(const tgw_panel* const* panels, int32_t n_
   }
   for (int i = 0; i < n_tile_shapes(); ++i) pl->grid_main.push_back(gemm_grid(i, pl->prec, kTest, pl->n_cu));
   pl->grid_w = gemm_grid(wgemm_tile(), wprec(pl->prec), kRaw, pl->n_cu);
+  if (g8_supported(pl->prec)) {
+    for (int i = 0; i < n_tile_shapes(); ++i) pl->grid_main8.push_back(gemm_grid(i, pl->prec, kTest, pl->n_cu, true));
+    pl->grid_w8 = gemm_grid(wgemm_tile(), wprec(pl->prec), kRaw, pl->n_cu, true);
+    if (o.tile < 0) {
+      auto cache8 = tune_cache_read();
+      auto it8 = cache8.find(tune_key(pl) + "/g8");
+      if (it8 != cache8.end() && it8->second >= 0 && it8->second < n_tile_shapes()) pl->tile8 = it8->second;
+    }
+  }
   if (o.tile >= 0) {
     pl->tile = o.tile;
+    pl->tile8 = o.tile;  // the wide shapes run shape 2 for 8-bit dosages
   } else {
     auto cache = tune_cache_read();
     auto it = cache.find(tune_key(pl));
@@ -539,9 +553,16 @@ tgw_status tgw::check_call(const tgw_plan* pl, const ScanCall& c, bool need_outs
   if (!pl) return fail(TGW_ERR_INVALID_ARG, "plan is NULL");
   if (!c.geno) return fail(TGW_ERR_INVALID_ARG, "d_geno is NULL");
   if (((uintptr_t)c.geno & 15) != 0) return fail(TGW_ERR_SHAPE, "d_geno must be 16-byte aligned");
-  if (c.code != TGW_CODE_DOSAGE && c.code != TGW_CODE_PLINK_BED) return fail(TGW_ERR_INVALID_ARG, "bad code");
+  if (c.code != TGW_CODE_DOSAGE && c.code != TGW_CODE_PLINK_BED && c.code != TGW_CODE_DOSAGE8)
+    return fail(TGW_ERR_INVALID_ARG, "bad code");
   if (c.row_bytes <= 0 || c.row_bytes % 16 != 0) return fail(TGW_ERR_SHAPE, "row_bytes must be a positive multiple of 16");
-  if (c.row_bytes < pl->n_pad / 4) return fail(TGW_ERR_SHAPE, "row_bytes < 16 * ceil(n_samples / 64)");
+  if (c.code == TGW_CODE_DOSAGE8) {
+    if (!g8_supported(pl->prec))
+      return fail(TGW_ERR_UNSUPPORTED, "8-bit dosages need TGW_PREC_FP32 or TGW_PREC_SPLIT_F16");
+    if (c.row_bytes < pl->n_pad) return fail(TGW_ERR_SHAPE, "row_bytes < 64 * ceil(n_samples / 64) for 8-bit dosages");
+  } else if (c.row_bytes < pl->n_pad / 4) {
+    return fail(TGW_ERR_SHAPE, "row_bytes < 16 * ceil(n_samples / 64)");
+  }
   if (c.n_markers < 0 || c.m_begin < 0 || c.m_begin > c.m_end || c.m_end > c.n_markers)
     return fail(TGW_ERR_SHAPE, "need 0 <= m_begin <= m_end <= n_markers");
   if (need_outs) {
@@ -575,6 +596,7 @@ static GemmArgs base_args(const tgw_plan* pl, const ScanCall& c, int64_t m0, int
   a.tail.capacity = pl->tail_cap;
   a.hits = pl->hits;
   a.m_begin = c.m_begin;
+  a.gunit = c.code == TGW_CODE_DOSAGE8 ? kDosage8Unit : 1.0f;
   return a;
 }
 
@@ -600,7 +622,8 @@ static hipError_t enqueue_block_stats(tgw_plan* pl, const ScanCall& c, int64_t m
   a.n_mtiles = (int)((nm + ws.tm() - 1) / ws.tm());
   a.raw_out = pl->wws;
   a.raw_ld = (int64_t)pl->n_panels * kSlots;
-  e = launch_gemm(wgemm_tile(), wprec(pl->prec), kRaw, a, pl->grid_w, s);
+  const bool g8 = c.code == TGW_CODE_DOSAGE8;
+  e = launch_gemm(wgemm_tile(), wprec(pl->prec), kRaw, a, g8 ? pl->grid_w8 : pl->grid_w, s, g8);
   if (e != hipSuccess) return e;
   return launch_finalize(pl->mstat, pl->wws, pl->invh, nm, pl->n_panels,
                          f16_scaled(pl->prec) ? 1.0f / kF16Scale : 1.0f, s);
@@ -608,12 +631,14 @@ static hipError_t enqueue_block_stats(tgw_plan* pl, const ScanCall& c, int64_t m
 
 static hipError_t enqueue_main(tgw_plan* pl, const ScanCall& c, int64_t m0, int64_t nm, int tile, hipStream_t s) {
   GemmArgs a = base_args(pl, c, m0, nm);
-  const TileShape ts = tile_shape_for(tile, pl->prec);
+  const bool g8 = c.code == TGW_CODE_DOSAGE8;
+  const TileShape ts = tile_shape_for(tile, pl->prec, g8);
+  const int grid = g8 ? pl->grid_main8[tile] : pl->grid_main[tile];
   a.cblocks = pl->d_cb_main;
   a.n_cblocks = pl->n_cb;
   a.n_ctiles = (pl->n_cb + ts.wn_frags - 1) / ts.wn_frags;
   a.n_mtiles = (int)((nm + ts.tm() - 1) / ts.tm());
-  if (!pl->profile) return launch_gemm(tile, pl->prec, kTest, a, pl->grid_main[tile], s);
+  if (!pl->profile) return launch_gemm(tile, pl->prec, kTest, a, grid, s, g8);
   hipEvent_t e0, e1;
   hipError_t e = hipEventCreate(&e0);
   if (e != hipSuccess) return e;
@@ -624,7 +649,7 @@ static hipError_t enqueue_main(tgw_plan* pl, const ScanCall& c, int64_t m0, int6
   }
   pl->prof_events.emplace_back(e0, e1);
   e = hipEventRecord(e0, s);
-  if (e == hipSuccess) e = launch_gemm(tile, pl->prec, kTest, a, pl->grid_main[tile], s);
+  if (e == hipSuccess) e = launch_gemm(tile, pl->prec, kTest, a, grid, s, g8);
   if (e == hipSuccess) e = hipEventRecord(e1, s);
   return e;
 }
@@ -656,7 +681,7 @@ hipError_t tgw::enqueue_scan_rows(tgw_plan* pl, const ScanCall& c, int64_t m_lo,
   for (int64_t m0 = m_lo; e == hipSuccess && m0 < m_hi; m0 += pl->MB) {
     const int64_t nm = std::min(pl->MB, m_hi - m0);
     e = enqueue_block_stats(pl, c, m0, nm, s);
-    if (e == hipSuccess) e = enqueue_main(pl, c, m0, nm, pl->tile, s);
+    if (e == hipSuccess) e = enqueue_main(pl, c, m0, nm, c.code == TGW_CODE_DOSAGE8 ? pl->tile8 : pl->tile, s);
   }
   return e;
 }
@@ -750,11 +775,12 @@ extern "C" tgw_status tgw_plan_autotune(tgw_plan* pl, const uint8_t* d_geno, int
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
-  int best = pl->tile;
+  const bool g8 = code == TGW_CODE_DOSAGE8;
+  int best = g8 ? pl->tile8 : pl->tile;
   double best_t = 1e300;
   hipError_t err = hipSuccess;
   for (int t = 0; t < n_tile_shapes() && err == hipSuccess; ++t) {
-    if (tile_alias(t, pl->prec) != t) continue;  // same kernel as an earlier shape
+    if (tile_alias(t, pl->prec, g8) != t) continue;  // same kernel as an earlier shape
     err = enqueue_main(pl, c, m_begin, nm, t, s);  // warm-up
     if (err != hipSuccess) break;
     const int reps = 3;
@@ -772,8 +798,13 @@ extern "C" tgw_status tgw_plan_autotune(tgw_plan* pl, const uint8_t* d_geno, int
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (err != hipSuccess) return hip_fail(err, "tgw_plan_autotune");
-  pl->tile = best;
-  tune_cache_write(tune_key(pl), best);
+  if (g8) {
+    pl->tile8 = best;
+    tune_cache_write(tune_key(pl) + "/g8", best);
+  } else {
+    pl->tile = best;
+    tune_cache_write(tune_key(pl), best);
+  }
   if (best_ms) *best_ms = best_t;
   return TGW_OK;
   TGW_GUARD_END
@@ -886,14 +917,16 @@ extern "C" tgw_status tgw_debug_contract(tgw_plan* pl, const uint8_t* d_geno, in
     sa.mstat = pl->mstat;
     HIP_TRY(launch_stats(sa, s));
     GemmArgs a = base_args(pl, c, m0, nm);
-    const TileShape ts = tile_shape_for(pl->tile, pl->prec);
+    const bool g8 = code == TGW_CODE_DOSAGE8;
+    const int tile = g8 ? pl->tile8 : pl->tile;
+    const TileShape ts = tile_shape_for(tile, pl->prec, g8);
     a.cblocks = pl->d_cb_main;
     a.n_cblocks = pl->n_cb;
     a.n_ctiles = (pl->n_cb + ts.wn_frags - 1) / ts.wn_frags;
     a.n_mtiles = (int)((nm + ts.tm() - 1) / ts.tm());
     a.raw_out = d_S + (m0 - m_begin) * lds;
     a.raw_ld = lds;
-    HIP_TRY(launch_gemm(pl->tile, pl->prec, kRaw, a, pl->grid_main[pl->tile], s));
+    HIP_TRY(launch_gemm(tile, pl->prec, kRaw, a, g8 ? pl->grid_main8[tile] : pl->grid_main[tile], s, g8));
   }
   return TGW_OK;
   TGW_GUARD_END

@@ -40,6 +40,7 @@ PREC_SPLIT_F8 = 3
 F16_SCALE = 4096.0  # the FP16 forms store 2^12 times the operand
 CODE_DOSAGE = 0
 CODE_PLINK_BED = 1
+CODE_DOSAGE8 = 2  # one byte per sample: q / 127 copies, 255 missing
 _PREC = {"fp32": PREC_FP32, "split": PREC_SPLIT, "split16": PREC_SPLIT_F16, "split8": PREC_SPLIT_F8,
          PREC_FP32: PREC_FP32, PREC_SPLIT: PREC_SPLIT, PREC_SPLIT_F16: PREC_SPLIT_F16,
          PREC_SPLIT_F8: PREC_SPLIT_F8}

@@ -9,6 +9,9 @@ their inputs from it without sharing any of the method.
 from .cohort import (  # noqa: F401
     CohortSpec,
     DOSAGE_TO_PLINK,
+    dosage8_row_bytes_for,
+    dosage8_rows_np,
+    dosage8_rows_torch,
     PanelSpec,
     causal_markers,
     SEED,

@@ -192,6 +192,66 @@ def pack_codes_np(codes: np.ndarray, row_bytes: int) -> np.ndarray:
     return (q[:, :, 0] | (q[:, :, 1] << 2) | (q[:, :, 2] << 4) | (q[:, :, 3] << 6)).astype(np.uint8)
 
 
+# ---------------------------------------------------------------------------
+# 8-bit dosages: imputed expected allele counts, q / 127 copies, 255 missing
+# ---------------------------------------------------------------------------
+DOSAGE8_MISSING = 255
+DOSAGE8_NOISE = 19  # imputation noise: uniform integer in [-19, 19], i.e. +-0.15 copies
+
+
+def dosage8_row_bytes_for(n: int) -> int:
+    return n_pad_for(n)
+
+
+def _dosage8_from(g_codes, noise_field, np_like):
+    """q = clip(127 g + e, 0, 254) with e = (u * 39 >> 16) - 19 from a 16-bit
+    uniform u; 255 where the code is missing.  Integer arithmetic only, so the
+    numpy and torch generators agree bit for bit."""
+    e = ((noise_field * (2 * DOSAGE8_NOISE + 1)) >> 16) - DOSAGE8_NOISE
+    q = np_like.clip(127 * g_codes + e, 0, 254)
+    return np_like.where(g_codes == CODE_MISSING, DOSAGE8_MISSING, q)
+
+
+def dosage8_rows_np(spec: CohortSpec, markers: Sequence[int], row_bytes: Optional[int] = None) -> np.ndarray:
+    """8-bit dosage rows (len(markers), row_bytes) uint8, sample i at byte i,
+    drawn around the 2-bit generator's allele counts (same missing calls);
+    padding bytes are 0."""
+    markers = np.asarray(markers, dtype=np.int64)
+    n = spec.n_samples
+    rb = dosage8_row_bytes_for(n) if row_bytes is None else row_bytes
+    g = geno_codes_np(spec, markers).astype(np.int64)
+    base = np.uint64(_stream_key(spec.seed, 5))
+    i = np.arange(n, dtype=np.uint64)[None, :]
+    with np.errstate(over="ignore"):
+        h = _sm64_np(base + ((markers.astype(np.uint64)[:, None] << np.uint64(32)) | i))
+    u = (h & np.uint64(0xFFFF)).astype(np.int64)
+    out = np.zeros((len(markers), rb), dtype=np.uint8)
+    out[:, :n] = _dosage8_from(g, u, np).astype(np.uint8)
+    return out
+
+
+def dosage8_rows_torch(spec: CohortSpec, m0: int, m1: int, device, row_bytes: Optional[int] = None,
+                       chunk: int = 4096, out=None):
+    """dosage8_rows_np for markers [m0, m1), generated on ``device``."""
+    import torch
+    n = spec.n_samples
+    rb = dosage8_row_bytes_for(n) if row_bytes is None else row_bytes
+    if out is None:
+        out = torch.zeros((m1 - m0, rb), dtype=torch.uint8, device=device)
+    for a in range(m0, m1, chunk):
+        b = min(m1, a + chunk)
+        g = geno_codes_torch(spec, a, b, device).to(torch.int64)
+        markers = torch.arange(a, b, dtype=torch.int64, device=device)
+        i = torch.arange(n, dtype=torch.int64, device=device)[None, :]
+        h = _sm64_torch(((markers[:, None] << 32) | i) + _signed(_stream_key(spec.seed, 5)))
+        u = h & 0xFFFF
+        del h
+        out[a - m0:b - m0, :n] = _dosage8_from(g, u, torch).to(torch.uint8)
+        if rb > n:
+            out[a - m0:b - m0, n:] = 0
+    return out
+
+
 # genotype code (0, 1, 2 copies; 3 missing) -> PLINK 1 .bed 2-bit code
 # (00 / 10 / 11 = 0 / 1 / 2 copies of the second allele, 01 missing)
 DOSAGE_TO_PLINK = np.array([0, 2, 3, 1], dtype=np.uint8)

@@ -217,6 +217,52 @@ def test_decode_brute_force():
                     assert G[m, i] == want
 
 
+def test_decode_dosage8_brute_force():
+    rng = np.random.default_rng(4)
+    rows = rng.integers(0, 256, size=(5, 70), dtype=np.uint8)
+    rows[0, :3] = [0, 254, 255]
+    n = 61  # bytes past the last sample are ignored
+    G = oracle.decode_dosage8(rows, n)
+    assert G.shape == (5, n)
+    for m in range(5):
+        for i in range(n):
+            q = int(rows[m, i])
+            if q == 255:
+                assert np.isnan(G[m, i])
+            else:
+                assert G[m, i] == q / 127.0
+    assert G[0, 0] == 0.0 and G[0, 1] == 2.0
+
+
+def test_brute_force_ols_fractional_dosages():
+    """The same least-squares pin with 8-bit dosages (values q / 127) and
+    missing bytes, including a marker whose observed dosages are all equal."""
+    rng = np.random.default_rng(77)
+    n, k = 90, 3
+    G0, C, Y = _tiny_cohort(rng, n, k, 12, 2, 0.0)
+    q = np.clip(np.rint(127 * (np.nan_to_num(G0) + rng.uniform(-0.3, 0.3, G0.shape))), 0, 254).astype(np.uint8)
+    q[rng.random(q.shape) < 0.08] = 255
+    q[0] = 127
+    q[0, :4] = 255  # monomorphic among observed
+    G = oracle.decode_dosage8(q, n)
+    out = oracle.scan(G, C, Y)
+    assert not out["marker_valid"][0] and np.all(np.isnan(out["t"][0]))
+    G_imp, _, _ = oracle.impute_mean(G)
+    checked = 0
+    for m in range(1, G.shape[0]):
+        assert out["marker_valid"][m]
+        for p in range(Y.shape[1]):
+            beta, se, t, df = _brute_ols(G_imp[m], C, Y[:, p])
+            np.testing.assert_allclose(out["beta"][m, p], beta, rtol=1e-9, atol=1e-12)
+            np.testing.assert_allclose(out["se"][m, p], se, rtol=1e-9)
+            np.testing.assert_allclose(out["t"][m, p], t, rtol=1e-9, atol=1e-10)
+            checked += 1
+    assert checked == 22
+    # scan_packed with the dosage code is the same computation
+    out2 = oracle.scan_packed(q, n, C, Y, oracle.CODE_DOSAGE8)
+    np.testing.assert_array_equal(out2["t"], out["t"])
+
+
 def test_degenerate_markers_and_phenotypes():
     rng = np.random.default_rng(9)
     n = 80

@@ -40,3 +40,21 @@ def test_packing_layout_and_rates():
     assert thr.min() >= 0.05 and thr.max() < 0.5
     obs = g[g < 3].astype(float)
     assert abs(obs.mean() / 2 - thr.mean()) < 0.01
+
+
+def test_dosage8_generator():
+    """8-bit dosages: numpy and torch agree bit for bit, missing bytes are the
+    2-bit generator's missing calls, observed bytes stay within the noise of
+    127 x the allele count, padding is zero."""
+    import torch
+    from synth import cohort_spec, dosage8_rows_np, dosage8_rows_torch, geno_codes_np
+    spec = cohort_spec("cfg1", n_samples=301)
+    a = dosage8_rows_np(spec, np.arange(50, 90))
+    b = dosage8_rows_torch(spec, 50, 90, "cpu", chunk=13).numpy()
+    np.testing.assert_array_equal(a, b)
+    assert a.shape == (40, 320) and np.all(a[:, 301:] == 0)
+    g = geno_codes_np(spec, np.arange(50, 90)).astype(np.int64)
+    q = a[:, :301].astype(np.int64)
+    np.testing.assert_array_equal(q == 255, g == 3)
+    obs = g != 3
+    assert np.all(np.abs(q[obs] - 127 * g[obs]) <= 19) and q[obs].max() <= 254
