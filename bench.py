@@ -186,6 +186,66 @@ def panel_scale_run(args, tgw, torch):
     return out
 
 
+def dosage_run(args, tgw, torch):
+    """The workload's cohort as 8-bit dosages (one byte per sample) over
+    args.dosage_markers markers, in the FP16 split form (the 16-bit form that
+    dosages run in), reduced outputs: autotune on the dosage rows, one warm-up
+    and one timed step with the main kernel timed by HIP events."""
+    from synth import cohort_spec, dosage8_rows_torch, panel_inputs
+    spec0 = cohort_spec(args.workload)
+    spec = spec0.__class__(**{**spec0.__dict__, "n_markers": args.dosage_markers})
+    N, M = spec.n_samples, spec.n_markers
+    t0 = time.perf_counter()
+    geno = torch.empty((M, (N + 63) // 64 * 64), dtype=torch.uint8, device="cuda")
+    step_m = max(1, -(-M // 4))
+    for a in range(0, M, step_m):
+        b = min(M, a + step_m)
+        dosage8_rows_torch(spec, a, b, "cuda", out=geno[a:b], chunk=16384)
+        torch.cuda.synchronize()
+        log(f"dosages: {b} / {M} markers")
+    C, Y = panel_inputs(spec, 0)
+    Cd, Yd = torch.from_numpy(C).cuda(), torch.from_numpy(Y).cuda()
+    del C, Y
+    P = Yd.shape[1]
+    best = tgw.make_best([P])
+    hits, hit_count = tgw.make_hits(1 << 20)
+    log(f"dosages: inputs generated in {time.perf_counter() - t0:.1f} s: N={N} M={M} P={P}")
+
+    def step(profile):
+        cov = tgw.fit_covariates(Cd)
+        plan = tgw.Plan([tgw.prepare_phenotypes(cov, Yd, "split16")])
+        best[0].zero_()
+        hit_count.zero_()
+        plan.set_hits(hits, hit_count, args.hit_threshold)
+        if profile:
+            plan.profile(True)
+        plan.scan(geno, [{"best": best[0]}], code=tgw.CODE_DOSAGE8)
+        return plan
+
+    if not args.no_autotune:
+        p0 = step(False)
+        p0.check()
+        p0.autotune(geno, [{"best": best[0]}], 0, min(M, 131072), code=tgw.CODE_DOSAGE8)
+    step(False).check()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = step(True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    plan.check()
+    ms, n = plan.profile_read()
+    ms /= max(1, n)
+    achieved = 2.0 * N * M * P / (ms / 1e3) / 1e12
+    out = {"workload": f"{args.workload} cohort as 8-bit dosages, N={N} M={M} P={P}, FP16 hi + lo, reduced outputs",
+           "value": M * P / dt, "unit": "tests/s", "ms_per_step": dt * 1e3, "main_kernel_ms": ms,
+           "main_kernel_tflops": achieved, "roofline_frac": achieved / PEAK_BF16_TFLOPS}
+    log(f"dosages: {dt * 1e3:.1f} ms/step, {M * P / dt:.3e} tests/s, main kernel {ms:.1f} ms, "
+        f"{achieved:.1f} TFLOP/s algorithmic")
+    del geno, Cd, Yd, best, hits, plan
+    torch.cuda.empty_cache()
+    return out
+
+
 def bed_stream_run(args, tgw, torch, tile):
     """The headline precision over args.bed_markers markers of the workload's
     cohort streamed from a PLINK 1 .bed file (written to a temporary directory,
@@ -268,6 +328,8 @@ def main():
                          "best test and a hit list at -log10 p >= --hit-threshold, no dense matrices")
     ap.add_argument("--hit-threshold", type=float, default=7.3)
     ap.add_argument("--copy-calibration", action="store_true", help="run only the 1 GiB copy used to scale counters")
+    ap.add_argument("--dosage-markers", type=int, default=262144,
+                    help="markers of the 8-bit dosage run beside the headline (0 = skip)")
     ap.add_argument("--bed-markers", type=int, default=262144,
                     help="markers of the .bed streaming run beside the headline (0 = skip)")
     ap.add_argument("--bed-block", type=int, default=32768)
@@ -401,6 +463,11 @@ def main():
     if args.bed_markers > 0 and not args.markers:
         bed_stream = bed_stream_run(args, tgw, torch, info["tile"])
 
+    # ---------------------------------------------------------------- 8-bit dosages
+    dosage = None
+    if args.dosage_markers > 0 and not args.markers:
+        dosage = dosage_run(args, tgw, torch)
+
     # ---------------------------------------------------------------- panel scale (P = 20,480)
     panel_scale = None
     if not args.no_panel_scale and args.workload == "cfg3" and not args.markers:
@@ -465,6 +532,7 @@ def main():
         "tail_tests": n_tail,
         "panel_scale": panel_scale,
         "bed_stream": bed_stream,
+        "dosage8_scan": dosage,
         "outputs": ("dense r, beta, se, t, -log10 p" if not reduced else
                     f"reduced: per-phenotype best test + hit list at -log10 p >= {args.hit_threshold} "
                     f"({int(hit_count.item())} hits in the last step)"),
