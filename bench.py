@@ -97,14 +97,12 @@ def cpu_baseline(spec, n_markers: int):
     import numpy as np
 
     import oracle
-    from synth import geno_codes_np, panel_inputs
+    from synth import geno_codes_np, pack_codes_np, panel_inputs, row_bytes_for
 
     C, Y = panel_inputs(spec)
-    codes = geno_codes_np(spec, np.arange(n_markers))
-    G = np.where(codes == 3, np.nan, codes.astype(np.float64))
-    Y64 = Y.astype(np.float64)
+    packed = pack_codes_np(geno_codes_np(spec, np.arange(n_markers)), row_bytes_for(spec.n_samples))
     t0 = time.perf_counter()
-    oracle.scan(G, C, Y64)
+    oracle.scan_packed(packed, spec.n_samples, C, Y)
     dt = time.perf_counter() - t0
     P = spec.panels[0].n_pheno
     return {
@@ -113,9 +111,18 @@ def cpu_baseline(spec, n_markers: int):
         "cores": blas_threads(),
         "kind": "oracle",
         "sample": f"markers [0, {n_markers}) x all {P} phenotypes at N={spec.n_samples}, K={spec.panels[0].n_cov}; "
-                  f"decode, impute, QR, panel prep, explicit residualization, FP64 GEMM, t, p; {dt:.1f} s",
+                  f"2-bit decode, impute, QR, panel prep, explicit residualization, FP64 GEMM, t, p; {dt:.1f} s",
         "seconds": dt,
     }
+
+
+def cpu_baseline_1thread(spec, n_markers: int):
+    """The same oracle sample on one BLAS thread."""
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1, user_api="blas"):
+        out = cpu_baseline(spec, n_markers)
+    out["cores"] = 1
+    return out
 
 
 def generate_genotypes(spec, torch, packed_rows_torch, row_bytes_for):
@@ -310,7 +317,7 @@ def bed_stream_run(args, tgw, torch, tile):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cfg3", choices=["cfg2", "cfg3", "cfg4", "cfg5"])
     ap.add_argument("--precision", default="split8", choices=["split", "split16", "split8", "fp32"])
@@ -443,6 +450,25 @@ def main():
     log(f"{args.precision}: {dt * 1e3:.1f} ms/step, {tests / dt:.3e} tests/s, main kernel {avg_launch_s * 1e3:.2f} ms "
         f"x {launches // len(prof)} launches, {achieved:.1f} TFLOP/s algorithmic, tail {n_tail}")
 
+    # ---------------------------------------------------------------- prepare alone, PCIe-inclusive rate
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    make_plan(args.precision, info["tile"])
+    torch.cuda.synchronize()
+    prepare_ms = (time.perf_counter() - t0) * 1e3
+    host = torch.empty(geno.shape, dtype=torch.uint8, pin_memory=True)
+    host.copy_(geno)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    geno.copy_(host, non_blocking=True)
+    torch.cuda.synchronize()
+    h2d_s = time.perf_counter() - t0
+    del host
+    log(f"prepare (fit + prepare + plan) {prepare_ms:.1f} ms; packed genotypes host-to-device {h2d_s * 1e3:.1f} ms "
+        f"({geno.numel() / h2d_s / 1e9:.1f} GB/s)")
+    side = {"prepare_ms": prepare_ms, "h2d_ms": h2d_s * 1e3, "h2d_gb_per_s": geno.numel() / h2d_s / 1e9,
+            "tests_per_s_including_h2d": tests / (dt + h2d_s)}
+
     # ---------------------------------------------------------------- other precisions beside
     beside = {}
     for prec in [x for x in args.beside.split(",") if x and x != args.precision]:
@@ -477,10 +503,13 @@ def main():
         panel_scale = panel_scale_run(args, tgw, torch)
 
     # ---------------------------------------------------------------- CPU baseline
-    cpu = None
+    cpu = cpu1 = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(spec, min(args.cpu_markers or max(256, 16384 * 2048 // P), M))
+        n_cpu = min(args.cpu_markers or max(256, 16384 * 2048 // P), M)
+        cpu = cpu_baseline(spec, n_cpu)
         log(f"cpu oracle: {cpu['value']:.3e} tests/s on {cpu['cores']} threads ({cpu['seconds']:.1f} s)")
+        cpu1 = cpu_baseline_1thread(spec, max(64, n_cpu // 16))
+        log(f"cpu oracle, one thread: {cpu1['value']:.3e} tests/s ({cpu1['seconds']:.1f} s)")
 
     traffic = load_traffic(args.workload, args.precision, info["tile"])
     line = {
@@ -525,6 +554,8 @@ def main():
             "avg_launch_ms": avg_launch_s * 1e3,
         },
         "cpu_baseline": None if cpu is None else {k: v for k, v in cpu.items() if k != "seconds"},
+        "cpu_baseline_1thread": None if cpu1 is None else {k: v for k, v in cpu1.items() if k != "seconds"},
+        "prepare_and_transfer": side,
         "fp32_scan": beside.get("fp32"),
         "split_scan": beside.get("split"),
         "split16_scan": beside.get("split16"),
