@@ -193,6 +193,74 @@ def panel_scale_run(args, tgw, torch):
     return out
 
 
+def batching_run(args, tgw, torch):
+    """The batching form (cfg5): 64 panels of log-uniform P in [32, 4096] and K
+    in [3, 20] sharing N = 23,000 x M = 200,000 genotypes, headline precision,
+    reduced outputs (best test per phenotype + one hit list).  One plan over all
+    panels, autotuned, its scan captured in a HIP graph: one warm-up and one
+    timed launch.  Beside it, the same panels one plan at a time (one launch
+    sequence each, same tile)."""
+    from synth import cohort_spec, packed_rows_torch, panel_inputs, row_bytes_for
+    spec = cohort_spec("cfg5")
+    N, M = spec.n_samples, spec.n_markers
+    t0 = time.perf_counter()
+    geno = generate_genotypes(spec, torch, packed_rows_torch, row_bytes_for)
+    panels, Ps, Ks = [], [], []
+    for j in range(len(spec.panels)):
+        C, Y = panel_inputs(spec, j)
+        cov = tgw.fit_covariates(torch.from_numpy(C).cuda())
+        panels.append(tgw.prepare_phenotypes(cov, torch.from_numpy(Y).cuda(), args.precision))
+        Ps.append(Y.shape[1])
+        Ks.append(C.shape[1])
+        del C, Y
+    P = sum(Ps)
+    log(f"batching: {len(panels)} panels prepared in {time.perf_counter() - t0:.1f} s: N={N} M={M} sum P={P}")
+    bests = tgw.make_best(Ps)
+    outs = [{"best": b} for b in bests]
+    hits, hit_count = tgw.make_hits(1 << 22)
+    plan = tgw.Plan(panels)
+    plan.set_hits(hits, hit_count, args.hit_threshold)
+    if not args.no_autotune:
+        plan.autotune(geno, outs, 0, min(M, 131072))
+    graph = plan.graph(geno, outs)
+
+    def reset():
+        for b in bests:
+            b.zero_()
+        hit_count.zero_()
+
+    reset()
+    graph.launch()
+    plan.check()
+    reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    graph.launch()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    n_tail = plan.check()
+    n_hits = int(hit_count.item())
+    tile = plan.info()["tile"]
+    singles = [tgw.Plan([p], tile=tile) for p in panels]
+    for sp, o in zip(singles, outs):  # warm-up
+        sp.scan(geno, [o])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for sp, o in zip(singles, outs):
+        sp.scan(geno, [o])
+    torch.cuda.synchronize()
+    dt1 = time.perf_counter() - t0
+    out = {"workload": f"cfg5: N={N} M={M}, {len(panels)} panels, sum P={P}, P {min(Ps)}-{max(Ps)}, "
+                       f"K {min(Ks)}-{max(Ks)}, reduced outputs, one graph-captured launch sequence",
+           "value": M * P / dt, "unit": "tests/s", "ms": dt * 1e3, "tile": tile, "hits": n_hits,
+           "tail_tests": n_tail, "one_panel_at_a_time_ms": dt1 * 1e3, "batched_speedup": dt1 / dt}
+    log(f"batching: {dt * 1e3:.1f} ms, {M * P / dt:.3e} tests/s; one panel at a time {dt1 * 1e3:.1f} ms "
+        f"({dt1 / dt:.2f}x)")
+    del graph, plan, singles, panels, geno, bests, outs, hits
+    torch.cuda.empty_cache()
+    return out
+
+
 def dosage_run(args, tgw, torch):
     """The workload's cohort as 8-bit dosages (one byte per sample) over
     args.dosage_markers markers, in the FP16 split form (the 16-bit form that
@@ -335,6 +403,7 @@ def main():
                          "best test and a hit list at -log10 p >= --hit-threshold, no dense matrices")
     ap.add_argument("--hit-threshold", type=float, default=7.3)
     ap.add_argument("--copy-calibration", action="store_true", help="run only the 1 GiB copy used to scale counters")
+    ap.add_argument("--no-batching", action="store_true", help="skip the cfg5 batching-form leg")
     ap.add_argument("--dosage-markers", type=int, default=262144,
                     help="markers of the 8-bit dosage run beside the headline (0 = skip)")
     ap.add_argument("--bed-markers", type=int, default=262144,
@@ -494,6 +563,11 @@ def main():
     if args.dosage_markers > 0 and not args.markers:
         dosage = dosage_run(args, tgw, torch)
 
+    # ---------------------------------------------------------------- batching form (cfg5)
+    batching = None
+    if not args.no_batching and args.workload == "cfg3" and not args.markers:
+        batching = batching_run(args, tgw, torch)
+
     # ---------------------------------------------------------------- panel scale (P = 20,480)
     panel_scale = None
     if not args.no_panel_scale and args.workload == "cfg3" and not args.markers:
@@ -564,6 +638,7 @@ def main():
         "panel_scale": panel_scale,
         "bed_stream": bed_stream,
         "dosage8_scan": dosage,
+        "batching": batching,
         "outputs": ("dense r, beta, se, t, -log10 p" if not reduced else
                     f"reduced: per-phenotype best test + hit list at -log10 p >= {args.hit_threshold} "
                     f"({int(hit_count.item())} hits in the last step)"),
