@@ -76,8 +76,8 @@ typedef enum {
  *                       against the genotype operand rounded to e4m3:
  *                       relative residual of the panel <= about 2^-16, one
  *                       FP16 pass plus one FP8 pass at twice the FP16 rate.
- *                       Runs on the wide tile shape only (every tile index
- *                       selects it).
+ *                       Runs on the wide tile shapes only (tiles 1 and 6
+ *                       select their own; every other index selects tile 0).
  * Covariate QR, phenotype norms and the extreme-tail p-values stay FP64. */
 typedef enum {
   TGW_PREC_FP32 = 0,

@@ -1398,6 +1398,39 @@ __global__ __launch_bounds__(NW * 64) void gemm_wide_kernel(GemmArgs a) {
           A8[4 * part + t] = (int)__builtin_amdgcn_perm(lut8[fm], lut8[fm], (src >> (2 * t)) & 0x03030303u);
       }
     };
+    // FP16 hi + FP8 lo with WMF = 2: the 2-bit fields of a code dword spread
+    // one per byte, Y[d] = (src >> 2d) & 0x03030303 for d = 0..3, are the e4m3
+    // table selectors as they stand and, paired byte by byte with Y + 0x04040404
+    // by one v_perm_b32, the FP16 table selectors; both decodes share one field
+    // extraction.  Y of the first code dword (K16 steps 0, 1) is made at the
+    // previous chunk's step 3, that of the second (steps 2, 3) at step 0.
+    auto spread = [&](const uint2* src2, int p, uint32_t (*Y)[4]) {
+#pragma unroll
+      for (int fm = 0; fm < WMF; ++fm) {
+        const uint32_t src = p ? src2[fm].y : src2[fm].x;
+#pragma unroll
+        for (int d = 0; d < 4; ++d) Y[fm][d] = (src >> (2 * d)) & 0x03030303u;
+      }
+    };
+    // step j (of the dword that Y spreads): samples t = 4 (j & 1) + d and t + 8
+    // sit in bytes (j & 1) and 2 + (j & 1) of Y[d]
+    auto decode_y = [&](const uint32_t (*Y)[4], int j, u32x4* A) {
+#pragma unroll
+      for (int fm = 0; fm < WMF; ++fm)
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+          const uint32_t y = Y[fm][d];
+          const uint32_t sel = __builtin_amdgcn_perm(y + 0x04040404u, y, (j & 1) ? 0x07030501u : 0x06020400u);
+          A[fm][d] = __builtin_amdgcn_perm(lut[fm].y, lut[fm].x, sel);
+        }
+    };
+    auto decode8_y = [&](const uint32_t (*Y0)[4], const uint32_t (*Y1)[4], int fm, i32x8& A8) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        A8[k] = (int)__builtin_amdgcn_perm(lut8[fm], lut8[fm], Y0[fm][k]);
+        A8[4 + k] = (int)__builtin_amdgcn_perm(lut8[fm], lut8[fm], Y1[fm][k]);
+      }
+    };
     auto read_b = [&](int st, int j, u32x4* bh, u32x4* bl) {
       const char* tile = smem + st * STAGE_BYTES;
 #pragma unroll
@@ -1430,9 +1463,16 @@ __global__ __launch_bounds__(NW * 64) void gemm_wide_kernel(GemmArgs a) {
     i32x8 A8[2], B8[WN];
     uint2 acur[WMF], anext[WMF];
     u32x4 araw[WMF];  // FP8 form: the next chunk's code rows, read a step early
+    constexpr bool SY = F8 && W2;  // shared selectors (spread / decode_y / decode8_y)
+    uint32_t Y0[SY ? WMF : 1][4], Y1[SY ? WMF : 1][4];  // selectors of the first / second code dword
     read_a(0, acur);
     read_b(0, 0, bh[0], bl[0]);
-    decode(acur, 0, A[0]);
+    if constexpr (SY) {
+      spread(acur, 0, Y0);
+      decode_y(Y0, 0, A[0]);
+    } else {
+      decode(acur, 0, A[0]);
+    }
     if constexpr (F8 && !W2) decode8(acur, 0, A8[0]);
 
     // the prologue's reads are complete before the loop; saying so keeps
@@ -1452,8 +1492,9 @@ __global__ __launch_bounds__(NW * 64) void gemm_wide_kernel(GemmArgs a) {
 #pragma unroll
           for (int q = 0; q < FNS; ++q) read_b8_one(st, j * FNS + q, B8[j * FNS + q]);  // used by this step
           if (j == 0) {
+            spread(acur, 1, Y1);
 #pragma unroll
-            for (int fm = 0; fm < WMF; ++fm) decode8(acur, fm, A8[fm]);  // both fragments, whole chunk
+            for (int fm = 0; fm < WMF; ++fm) decode8_y(Y0, Y1, fm, A8[fm]);  // both fragments, whole chunk
           }
         }
         if (F8 && j == 2) {
@@ -1464,7 +1505,10 @@ __global__ __launch_bounds__(NW * 64) void gemm_wide_kernel(GemmArgs a) {
         }
         if (j < 3) {
           read_b(st, j + 1, bh[ns], bl[ns]);
-          decode(acur, j + 1, A[ns]);
+          if constexpr (SY)
+            decode_y(j + 1 < 2 ? Y0 : Y1, j + 1, A[ns]);
+          else
+            decode(acur, j + 1, A[ns]);
         } else {
           // own copies of chunk ch+1 done (the NSTAGE-2 later chunks may
           // still be in flight) and own LDS reads of this chunk done; then
@@ -1478,7 +1522,12 @@ __global__ __launch_bounds__(NW * 64) void gemm_wide_kernel(GemmArgs a) {
           // direct-to-LDS load is held until that load completes
           read_b(st1, 0, bh[ns], bl[ns]);
           if constexpr (!F8) dma(ch + NSTAGE, st);  // the FP8 form copies beside its lo MFMAs
-          decode(anext, 0, A[ns]);
+          if constexpr (SY) {
+            spread(anext, 0, Y0);
+            decode_y(Y0, 0, A[ns]);
+          } else {
+            decode(anext, 0, A[ns]);
+          }
         }
 #pragma unroll
         for (int fn = 0; fn < WN; ++fn)
@@ -1725,7 +1774,7 @@ static const void* gemm_fn_g8(int idx) {  // 8-bit dosages: register-staged shap
       case 3: return (const void*)gemm_kernel<PREC, 4, 2, 4, MODE, true>;
       case 4: return (const void*)gemm_kernel<PREC, 8, 1, 4, MODE, true>;
       case 5: return (const void*)gemm_kernel<PREC, 8, 2, 2, MODE, true>;
-      case 7: return (const void*)gemm_kernel<PREC, 8, 2, 1, MODE, true>;
+      case kWShape: return (const void*)gemm_kernel<PREC, 8, 2, 1, MODE, true>;
       default: return (const void*)gemm_kernel<PREC, 8, 2, 4, MODE, true>;
     }
   }
@@ -1753,16 +1802,17 @@ static const void* gemm_fn(int idx) {
       case 6:  // the 256 x 256 wide shape exists for the FP8 lo form only
         if constexpr (PREC != kFP32) return (const void*)gemm_wide_kernel<PREC, MODE, 4, 4>;
         return (const void*)gemm_kernel<PREC, 8, 2, 4, MODE>;
-      case 7: return (const void*)gemm_kernel<PREC, 8, 2, 1, MODE>;
+      case kWShape: return (const void*)gemm_kernel<PREC, 8, 2, 1, MODE>;
     }
     return nullptr;
   }
 }
 
 static TileShape effective_shape(int idx, int prec, bool g8 = false) {
-  if (g8) return kShapes[(idx <= 1 || idx == 6) ? 2 : idx];
-  if (prec == kSplit8) return kShapes[idx == 1 ? 1 : idx == 6 ? 6 : 0];
-  if ((idx <= 1 || idx == 6) && prec == kFP32) return kShapes[2];
+  const bool wide = idx <= 1 || idx == 6;
+  if (g8) return kShapes[wide ? 2 : idx];
+  if (prec == kSplit8) return kShapes[(idx == 1 || idx == 6) ? idx : 0];
+  if (wide && prec == kFP32) return kShapes[2];
   if (idx == 6) return kShapes[0];
   return kShapes[idx];
 }
