@@ -456,3 +456,25 @@ def test_phenotype_dependent_missingness(tgw, precision):
         compare(res[0], ref, ref["df"], f"dependent missingness {precision} ", p_tol=5e-4)
     else:
         compare(res[0], ref, ref["df"], f"dependent missingness {precision} ")
+
+
+@pytest.fixture(scope="module")
+def biobank_cohort():
+    spec = cohort_spec("cfg1", n_samples=500_001, n_markers=640)
+    codes, packed, C, Y = cohort_arrays(spec, np.arange(spec.n_markers))
+    return spec, codes, packed, C, Y, oracle_scan(codes, C, Y)
+
+
+@pytest.mark.parametrize("precision", ["split8", "fp32"])
+def test_biobank_scale_cohort(tgw, biobank_cohort, precision):
+    """N = 500,001 samples (a biobank-sized cohort, ragged against the 64-sample
+    chunk), 640 markers (a ragged 512-marker tile), K = 4: every output against
+    the oracle; the FP32 accumulation runs over 7,813 sample chunks."""
+    spec, codes, packed, C, Y, ref = biobank_cohort
+    n = spec.n_samples
+    say(f"case: biobank-scale cohort {precision} N={n} M={spec.n_markers}")
+    res, n_tail, _ = gpu_scan(C, [Y], packed, precision)
+    assert ref["df"] == n - 6
+    err = compare(res[0], ref, ref["df"], f"N=500001 {precision} ")
+    assert n_tail == int(np.sum(np.abs(ref["t"]) > 40))
+    say(f"[N=500001 {precision}] {err}")
