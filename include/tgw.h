@@ -154,7 +154,9 @@ typedef struct {
 typedef struct {
   int64_t block_markers; /* markers per internal block (0 = automatic)          */
   int64_t tail_capacity; /* extreme-tail list entries (0 = 1<<20)                */
-  int32_t tile;          /* tile shape index, < 0 = default (see tgw_plan_info)  */
+  int32_t tile;          /* tile shape index, < 0 = default (see tgw_plan_info);
+                            also the shape of 8-bit dosage scans, where the wide
+                            shapes run the register-staged shape 2             */
   int32_t reserved;
 } tgw_plan_options;
 
