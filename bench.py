@@ -47,6 +47,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+# algorithmic ceiling of each precision form at published dense peaks: the
+# split forms run two passes per algorithmic FLOP
+FORM_CEILING_TFLOPS = {"split8": 1.0 / (1.0 / 2500.0 + 1.0 / 5000.0), "split": 1250.0, "split16": 1250.0,
+                       "fp32": 157.3}
 WIDE_TILES = (0, 1, 6)  # persistent LDS-ring kernel shapes (the split forms only)
 
 
@@ -624,6 +628,11 @@ def main():
                       + " (contraction + fused epilogue)",
             "peak_basis": "dense 16-bit MFMA; the FP8 lo pass of split8 runs at twice that rate"
                           if args.precision == "split8" else "dense MFMA of the operand type",
+            # the form's own ceiling at published peaks: one FP16 pass (2.5 PFLOP/s) plus one FP8
+            # pass (5.0 PFLOP/s) per algorithmic FLOP, 1 / (1/2.5 + 1/5) = 1.67 PFLOP/s
+            "form_ceiling": FORM_CEILING_TFLOPS.get(args.precision),
+            "frac_of_form_ceiling": achieved / FORM_CEILING_TFLOPS[args.precision]
+                                    if args.precision in FORM_CEILING_TFLOPS else None,
             "algorithmic_flops_per_launch": flops_per_launch,
             "avg_launch_ms": avg_launch_s * 1e3,
         },
