@@ -106,7 +106,8 @@ typedef struct tgw_graph tgw_graph;           /* a captured tgw_scan call     */
 
 /* Output buffers of one panel for one tgw_scan call.  Each array is
  * (m_end - m_begin) rows x n_pheno columns, row-major with row stride `ld`
- * elements (ld >= n_pheno): element (m - m_begin, p) holds the statistic of
+ * elements (n_pheno <= ld <= 2^22; a larger stride is TGW_ERR_SHAPE when a
+ * dense array is given): element (m - m_begin, p) holds the statistic of
  * marker m and phenotype p.  Any pointer may be NULL (not computed/written).
  *   r        partial correlation of g_m and y_p given [1 | C], in [-1, 1]
  *   beta     OLS coefficient of g_m (phenotype units per allele)

@@ -29,6 +29,7 @@ constexpr double kMarkerTol = 1e-4;
 constexpr float kTMax = 40.0f;        // |t| beyond this goes to the FP64 tail
 constexpr int kTabPerUnit = 32;       // nodes per unit of |t|
 constexpr int kTabNodes = 40 * 32 + 2;
+constexpr int kTabIntervals = kTabNodes - 1;  // one cubic per interval between nodes
 
 // kSplit8: FP16 hi term of 2^12 y against FP16 genotypes, plus the FP8 e4m3
 // lo term (scaled per column by a power of two) against FP8 genotypes
@@ -59,7 +60,7 @@ struct PanelDev {
   const float* scale;   // s_p = ||Y_res,p||
   const float* invny;   // 1 / ||(I - QQ^T) y_op,p||  (NaN for degenerate columns)
   const float* cw;      // [P_pad][32]: (-sum_i y_op, -q_k^T y_op for k >= 1, 0 ...)
-  const float2* table;  // Hermite nodes of -log10 p(|t|): (f, f' / kTabPerUnit)
+  const float4* table;  // per interval k: -log10 p(|t|) = c0 + c1 s + c2 s^2 + c3 s^3, s = 32|t| - k
   const uint8_t* lscale; // FP8 form: E8M0 scale of each column's lo term (NULL otherwise)
   int64_t n_pheno;
   float df;
@@ -67,6 +68,10 @@ struct PanelDev {
   float inv_sqrt_df;
   int32_t q;
 };
+
+// largest output row stride: a workgroup's rows of one column block then lie
+// within 2^31 bytes of its first element, so stores take 32-bit offsets
+constexpr int64_t kMaxOutLd = int64_t(1) << 22;
 
 struct OutDev {
   float* r;
@@ -173,7 +178,7 @@ hipError_t launch_prep(const void* Y, int y_fp64, int64_t ldy, int64_t n, int64_
                        uint8_t* lscale, int32_t* flags, hipStream_t s);
 hipError_t launch_set_operand(const float* V, int64_t ldv, int64_t n, int64_t n_pad, int64_t P, int prec,
                               void* yop, uint8_t* lscale, hipStream_t s);
-hipError_t launch_table(float2* table, double df, hipStream_t s);
+hipError_t launch_table(float4* table, double df, hipStream_t s);
 hipError_t launch_stats(const StatsArgs& a, hipStream_t s);
 hipError_t launch_finalize(const MarkerStat* ms, float* wws, float* invh, int64_t nm, int n_panels, float wscale,
                            hipStream_t s);

@@ -15,6 +15,8 @@
 
 #include <math.h>
 
+#include <type_traits>
+
 namespace tgw {
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
@@ -274,29 +276,44 @@ __device__ double ln_pdf_t(double t, double df) {
          0.5 * (df + 1.0) * log1p(t * t / df);
 }
 
-__global__ void table_kernel(float2* table, double df) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= kTabNodes) return;
-  const double t = (double)k / kTabPerUnit;
+// -log10 p of |t| and its derivative in |t|, in FP64
+__device__ void nlog10p_and_slope(double t, double df, double& f, double& fp) {
   const double lnp = ln_p_two_sided(t, df);
-  const double f = -lnp / M_LN10;
-  const double fp = 2.0 * exp(ln_pdf_t(t, df) - lnp) / M_LN10;  // d(-log10 p)/d|t|
-  table[k] = make_float2((float)f, (float)(fp / kTabPerUnit));
+  f = -lnp / M_LN10;
+  fp = 2.0 * exp(ln_pdf_t(t, df) - lnp) / M_LN10;
 }
 
-// cubic Hermite interpolation of -log10 p at |t| <= kTMax
-__device__ inline float table_nlog10p(const float2* __restrict__ tab, float at) {
+// the cubic Hermite interpolant of -log10 p on interval k (nodes k and k + 1,
+// values and slopes), written as its power-series coefficients in the local
+// variable s in [0, 1] so that the epilogue evaluates it with three FMAs
+__global__ void table_kernel(float4* table, double df) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= kTabIntervals) return;
+  double f0, d0, f1, d1;
+  nlog10p_and_slope((double)k / kTabPerUnit, df, f0, d0);
+  nlog10p_and_slope((double)(k + 1) / kTabPerUnit, df, f1, d1);
+  d0 /= kTabPerUnit;  // slopes per unit of s
+  d1 /= kTabPerUnit;
+  table[k] = make_float4((float)f0, (float)d0, (float)(3.0 * (f1 - f0) - 2.0 * d0 - d1),
+                         (float)(2.0 * (f0 - f1) + d0 + d1));
+}
+
+// interval coefficients as a plain vector type (HIP's float4 class has no
+// copy from an LDS reference); the wide kernel's epilogue reads a copy of the
+// table in LDS
+typedef float tab4 __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(3))) tab4* LdsTable;
+
+// cubic Hermite interpolation of -log10 p at |t| <= kTMax (TabPtr: the global
+// table or its LDS copy)
+template <class TabPtr>
+__device__ inline float table_nlog10p(TabPtr tab, float at) {
   const float x = at * (float)kTabPerUnit;
   int k = (int)x;
-  k = k > kTabNodes - 2 ? kTabNodes - 2 : k;
+  k = k > kTabIntervals - 1 ? kTabIntervals - 1 : k;
   const float s = x - (float)k;
-  const float2 n0 = tab[k], n1 = tab[k + 1];
-  const float s2 = s * s, s3 = s2 * s;
-  const float h00 = 2.f * s3 - 3.f * s2 + 1.f;
-  const float h10 = s3 - 2.f * s2 + s;
-  const float h01 = -2.f * s3 + 3.f * s2;
-  const float h11 = s3 - s2;
-  return n0.x * h00 + n0.y * h10 + n1.x * h01 + n1.y * h11;
+  const tab4 c = tab[k];
+  return fmaf(fmaf(fmaf(c.w, s, c.z), s, c.y), s, c.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -802,41 +819,15 @@ __device__ __forceinline__ f32x16 mfma16(const u32x4& a, const u32x4& b, const f
   }
 }
 
-// -log10 p, t, beta, SE and r of one test; writes the requested outputs,
-// appends the test to the hit list when it reaches the threshold, and
-// returns |t| for the per-column best (NaN when undefined).  -log10 p is
-// evaluated only where an output needs it: for the dense matrix, for tests
-// that may reach the hit threshold, and (in FP64, by the tail kernel) for
-// |t| > 40.
-__device__ __forceinline__ float epilogue_one(float S, float invh, float invny, float sp, const PanelDev& pd,
-                                              const OutDev& od, int64_t o, int64_t row, int j, int64_t p,
-                                              const TailDev& tail, const HitDev& hits, int64_t marker) {
-  float r = S * invh * invny;
-  if (r > 1.0f) r = 1.0f;
-  if (r < -1.0f) r = -1.0f;
-  const float omr2 = (1.0f - r) * (1.0f + r);
-  const float t = r * pd.sqrt_df * rsqrtf(omr2);
-  if (od.r) gstore(od.r + o, r);
-  if (od.beta) gstore(od.beta + o, r * sp * invh);
-  if (od.se) gstore(od.se + o, sp * invh * sqrtf(omr2) * pd.inv_sqrt_df);
-  if (od.t) gstore(od.t + o, t);
-  const float at = fabsf(t);
-  if (!(od.nl || od.best || hits.entries)) return at;
-  const bool hit_cand = hits.entries && at >= hits.t_floor;
-  if (!od.nl && !hit_cand && at <= kTMax) return at;  // best tracks |t|; no -log10 p needed here
-  float nl, track;
-  bool to_tail = false;
-  if (at <= kTMax) {
-    nl = track = table_nlog10p(pd.table, at);
-  } else if (at != at) {
-    nl = track = at;  // NaN
-  } else if (at == INFINITY) {
-    nl = track = INFINITY;
-  } else {
-    track = table_nlog10p(pd.table, kTMax);  // lower bound until the tail kernel runs
-    nl = INFINITY;
-    to_tail = true;
-  }
+// the rare part of a test's epilogue: |t| > 40 goes to the FP64 tail list
+// (its -log10 p written as +inf until the tail kernel replaces it; with the
+// list full, the table's value at 40 stands as a lower bound and the call
+// reports the overflow), and a test at or above the hit threshold is
+// appended to the hit list (for tail entries the tail kernel decides).
+template <class TabPtr>
+__device__ __forceinline__ void epilogue_rare(bool to_tail, float nl, float at, float r, TabPtr tab, float* nl_out,
+                                           int64_t row, int j, int64_t p, const TailDev& tail, const HitDev& hits,
+                                           int64_t marker) {
   if (to_tail) {
     const unsigned long long idx = atomicAdd(tail.count, 1ull);
     if (idx < (unsigned long long)tail.capacity) {
@@ -846,43 +837,171 @@ __device__ __forceinline__ float epilogue_one(float S, float invh, float invny, 
       e.col = (int32_t)p;
       e.r = r;
       e.pad = 0;
-      tail.entries[idx] = e;  // the tail kernel writes -log10 p and decides the hit
-    } else {
-      nl = track;  // lower bound; the call reports the overflow
-      to_tail = false;
+      tail.entries[idx] = e;
+      if (nl_out) gstore(nl_out, INFINITY);
+      return;
     }
+    nl = table_nlog10p(tab, kTMax);
+    if (nl_out) gstore(nl_out, nl);
   }
-  if (hit_cand && !to_tail && nl >= hits.threshold) append_hit(hits, marker, j, p, nl, r);
-  if (od.nl) gstore(od.nl + o, nl);
-  return at;
+  if (hits.entries && at >= hits.t_floor && nl >= hits.threshold) append_hit(hits, marker, j, p, nl, r);
 }
 
 // finish one 32-column block of a wave's staged accumulators (stage holds
 // rows 0 .. 32*WMF-1 of the wave's fragments, 32 columns each): lanes run
 // along columns, two rows at a time; the per-column best over the rows is
-// reduced in registers and merged with one atomic per column
-template <int WMF>
+// reduced in registers and merged with one atomic per column.
+// invny and sp are this lane's column values (sp already per genotype unit).
+// IhPtr: GlobalRows reads each row's 1/||g_res|| from global memory; an LDS
+// pointer gives the wave's rows, copied there ahead of the output stores
+// (on this chip a load issued after stores waits for them to complete, so
+// loads inside the row loop would serialise behind the previous row's stores).
+struct GlobalRows {};
+__device__ __forceinline__ float* at_byte(float* base, uint32_t ob) { return (float*)((char*)base + ob); }
+typedef const __attribute__((address_space(3))) float* LdsRows;
+
+template <int WMF, class TabPtr, class IhPtr>
 __device__ __forceinline__ void finish_block(const float* stage, const GemmArgs& a, const ColBlock& blk,
-                                             int64_t rowbase, int h, int r32) {
+                                             int64_t rowbase, int h, int r32, TabPtr tab, IhPtr ih, float invny,
+                                             float sp) {
+  if constexpr (!std::is_same<IhPtr, GlobalRows>::value) {
+    // the lane's place from a fresh v_mbcnt: a lane index kept in a register
+    // across the whole kernel gets spilled, and its reload just before the row
+    // loop makes the compiler wait in every iteration for the earlier stores
+    int lane;
+    asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(lane));
+    h = lane >> 5;
+    r32 = lane & 31;
+  }
+  static_assert(WMF <= 4, "rows of a block within 32-bit store offsets");
   const int j = blk.panel;
   const PanelDev pd = a.panels[j];
   const OutDev od = a.outs[j];
   const int64_t p = blk.col0 + r32;
   const bool colok = r32 < blk.ncol;
-  const float invny = colok ? gload<float>(pd.invny + p) : 0.f;
-  const float sp = colok ? gload<float>(pd.scale + p) * a.gunit : 0.f;  // beta and SE per genotype unit
+  // dense outputs rebased at (first row, first column) of the block: with
+  // ld <= 2^22 and at most 128 rows every store is within 2^31 bytes of it
+  // (held in scalar registers, so that a store is scalar base + vector offset)
+  OutDev odb = od;
+  {
+    const int64_t base = (a.out_row0 + rowbase) * od.ld + blk.col0;
+    auto rebase = [base](float* q) {
+      const uint64_t v = q ? (uint64_t)(q + base) : 0;
+      const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+      const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+      return (float*)(((uint64_t)hi << 32) | lo);
+    };
+    odb.r = rebase(od.r);
+    odb.beta = rebase(od.beta);
+    odb.se = rebase(od.se);
+    odb.t = rebase(od.t);
+    odb.nl = rebase(od.nl);
+  }
+  if constexpr (!std::is_same<IhPtr, GlobalRows>::value) {
+    // the loads above (vector loads: the kernel writes global memory, so
+    // they cannot go through the scalar cache) are waited for once here;
+    // waited for at their first use they would put a full wait for the
+    // previous rows' stores into every iteration
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0); expcnt and lgkmcnt unconstrained
+  }
   float bv = -1.0f;  // largest |t| of this lane's rows (-log10 p is increasing in |t| at fixed df)
   int64_t bm = 0;
-  for (int rr = h; rr < WMF * 32; rr += 2) {
-    const int64_t mr = rowbase + rr;
-    if (colok && mr < a.nm) {
-      const float invh = gload<float>(a.invh + mr * a.n_panels + j);
-      const int64_t row = a.out_row0 + mr;
-      const float at = epilogue_one(stage[rr * 32 + r32], invh, invny, sp, pd, od, row * od.ld + p, row, j, p,
-                                    a.tail, a.hits, a.m_begin + row);
-      if (at > bv) {
-        bv = at;
-        bm = a.m_begin + row;
+  // -log10 p is needed for the dense output, for hit candidates, and (in
+  // FP64, from the tail kernel) for |t| > 40 whenever any reduced output or
+  // the dense output asks for it
+  const bool need_p = od.nl || od.best || a.hits.entries;
+  const bool need_tab = od.nl || a.hits.entries;
+  const float hit_floor = a.hits.entries ? a.hits.t_floor : __builtin_nanf("");  // NaN: no |t| reaches it
+  const float sqrt_df = pd.sqrt_df, inv_sqrt_df = pd.inv_sqrt_df;
+  // R rows at a time: their LDS reads and table reads are in flight together
+  constexpr int R = 4;
+  static_assert((WMF * 16) % R == 0, "row groups");
+  for (int g = 0; g < WMF * 16; g += R) {
+    float Sv[R], ihv[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int rr = h + 2 * (g + i);
+      Sv[i] = stage[rr * 32 + r32];
+      if constexpr (std::is_same<IhPtr, GlobalRows>::value) {
+        int64_t mr = rowbase + rr;
+        mr = mr < a.nm ? mr : a.nm - 1;
+        ihv[i] = gload<float>(a.invh + mr * a.n_panels + j);
+      } else {
+        ihv[i] = ih[rr];
+      }
+    }
+    float rv[R], atv[R];
+    bool okv[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int rr = h + 2 * (g + i);
+      okv[i] = colok && rowbase + rr < a.nm;
+      const float invh = ihv[i];
+      float r = Sv[i] * invh * invny;
+      if (r > 1.0f) r = 1.0f;
+      if (r < -1.0f) r = -1.0f;
+      // 1 - r^2 is 0 or at least about 2^-24, never subnormal: the hardware
+      // square root and reciprocal square root (1 ulp) serve as they are
+      const float omr2 = (1.0f - r) * (1.0f + r);
+      const float t = r * sqrt_df * __builtin_amdgcn_rsqf(omr2);
+      const uint32_t ob = ((uint32_t)rr * (uint32_t)od.ld + (uint32_t)r32) * 4u;
+      if (okv[i]) {
+        if (odb.r) gstore(at_byte(odb.r, ob), r);
+        if (odb.beta) gstore(at_byte(odb.beta, ob), r * sp * invh);
+        if (odb.se) gstore(at_byte(odb.se, ob), sp * invh * __builtin_amdgcn_sqrtf(omr2) * inv_sqrt_df);
+        if (odb.t) gstore(at_byte(odb.t, ob), t);
+      }
+      rv[i] = r;
+      atv[i] = fabsf(t);
+      if (okv[i] && atv[i] > bv) {  // NaN never enters
+        bv = atv[i];
+        bm = a.m_begin + a.out_row0 + rowbase + rr;
+      }
+    }
+    if (need_p) {
+      float nlv[R];
+      if (need_tab) {  // the table at min(|t|, 40) (NaN reads the last interval): R reads in flight together
+        tab4 cv[R];
+        float sv[R];
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+          const float x = fminf(atv[i], kTMax) * (float)kTabPerUnit;
+          int k = (int)x;
+          k = k > kTabIntervals - 1 ? kTabIntervals - 1 : k;
+          sv[i] = x - (float)k;
+          cv[i] = tab[k];
+        }
+#pragma unroll
+        for (int i = 0; i < R; ++i) nlv[i] = fmaf(fmaf(fmaf(cv[i].w, sv[i], cv[i].z), sv[i], cv[i].y), sv[i], cv[i].x);
+      } else {
+#pragma unroll
+        for (int i = 0; i < R; ++i) nlv[i] = 0.0f;
+      }
+      uint32_t rare = 0;
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        const float at = atv[i];
+        // |t| <= 40: the table; NaN and +inf carry over; 40 < |t| < inf: the tail
+        const bool to_tail = okv[i] && at > kTMax && at != INFINITY;
+        const float nl = at <= kTMax ? nlv[i] : at;
+        nlv[i] = nl;
+        if (okv[i] && !to_tail && odb.nl) gstore(at_byte(odb.nl, ((uint32_t)(h + 2 * (g + i)) * (uint32_t)od.ld + (uint32_t)r32) * 4u), nl);
+        const bool hit = okv[i] && !to_tail && at >= hit_floor && nl >= a.hits.threshold;
+        rare |= (to_tail || hit) ? 1u << i : 0u;
+      }
+      if (__builtin_amdgcn_ballot_w64(rare != 0)) {
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+          if (rare & (1u << i)) {
+            const int rr = h + 2 * (g + i);
+            const int64_t row = a.out_row0 + rowbase + rr;
+            const uint32_t ob = ((uint32_t)rr * (uint32_t)od.ld + (uint32_t)r32) * 4u;
+            const float at = atv[i];
+            epilogue_rare(at > kTMax && at != INFINITY, nlv[i], at, rv[i], tab,
+                          odb.nl ? at_byte(odb.nl, ob) : (float*)nullptr, row, j, p, a.tail, a.hits, a.m_begin + row);
+          }
+        }
       }
     }
   }
@@ -896,7 +1015,7 @@ __device__ __forceinline__ void finish_block(const float* stage, const GemmArgs&
     if (h == 0 && colok && bv >= 0.0f) {
       // beyond |t| = 40 the table's value at 40 is a lower bound that the
       // FP64 tail kernel replaces
-      const float nl = bv == INFINITY ? INFINITY : table_nlog10p(pd.table, bv <= kTMax ? bv : kTMax);
+      const float nl = bv == INFINITY ? INFINITY : table_nlog10p(tab, bv <= kTMax ? bv : kTMax);
       atomicMax(od.best + p, best_pack(nl, bm));
     }
   }
@@ -1201,7 +1320,12 @@ __global__ __launch_bounds__(NW * 64) void gemm_kernel(GemmArgs a) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        finish_block<WMF>(stage, a, a.cblocks[cb], rowbase, h, r32);
+        const ColBlock blk = a.cblocks[cb];
+        const PanelDev& pdb = a.panels[blk.panel];
+        const bool colok = r32 < blk.ncol;
+        const float invny = colok ? gload<float>(pdb.invny + blk.col0 + r32) : 0.f;
+        const float sp = colok ? gload<float>(pdb.scale + blk.col0 + r32) * a.gunit : 0.f;
+        finish_block<WMF>(stage, a, blk, rowbase, h, r32, (const tab4*)pdb.table, GlobalRows{}, invny, sp);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -1269,7 +1393,15 @@ __global__ __launch_bounds__(NW * 64) void gemm_wide_kernel(GemmArgs a) {
   constexpr int DS_STEP = F8 ? WN : 2 * WN;              // fragment reads per step
   static_assert(NW * WMF * 32 * 32 * 4 <= LDS_BYTES, "epilogue staging must fit");
   static_assert((NSTAGE - 2) * CHUNK_OPS < 64, "vmcnt range");
-  __shared__ __attribute__((aligned(16))) char smem[LDS_BYTES];
+  // past the stages: each row's 1/||g_res|| of the current column panel and,
+  // where it fits, that panel's p-value table; the epilogue then reads
+  // nothing from global memory between its output stores
+  constexpr int IH_BYTES = TM * 4;
+  constexpr int TAB_BYTES = kTabIntervals * 16;
+  constexpr bool LT = LDS_BYTES + IH_BYTES + TAB_BYTES <= 160 * 1024;
+  static_assert(WMF % 2 == 0 && LDS_BYTES + IH_BYTES <= 160 * 1024, "epilogue rows in LDS");
+  __shared__ __attribute__((aligned(16))) char smem[LDS_BYTES + IH_BYTES + (LT ? TAB_BYTES : 0)];
+  int tab_panel = -1;  // panel whose table is in LDS (uniform)
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -1690,6 +1822,42 @@ __global__ __launch_bounds__(NW * 64) void gemm_wide_kernel(GemmArgs a) {
           }
       }
     } else {
+      // this lane's column values of each block, read ahead of the stores
+      float cinv[WN], csp[WN];
+#pragma unroll
+      for (int fn = 0; fn < WN; ++fn) {
+        const int cb = ctile * WN + fn;
+        const ColBlock blk = a.cblocks[cb < a.n_cblocks ? cb : ctile * WN];
+        const PanelDev& pdb = a.panels[blk.panel];
+        const bool colok = cb < a.n_cblocks && r32 < blk.ncol;
+        cinv[fn] = colok ? gload<float>(pdb.invny + blk.col0 + r32) : 0.f;
+        csp[fn] = colok ? gload<float>(pdb.scale + blk.col0 + r32) * a.gunit : 0.f;
+      }
+      // the wave's rows' 1/||g_res|| for panel j, one or two rows per lane
+      float* ihl = (float*)(smem + LDS_BYTES) + __builtin_amdgcn_readfirstlane(wave) * (WMF * 32);
+      auto load_rows = [&](int j) {
+#pragma unroll
+        for (int k = 0; k < WMF / 2; ++k) {
+          int64_t mr = rowbase + 64 * k + lane;
+          mr = mr < a.nm ? mr : a.nm - 1;
+          ihl[64 * k + lane] = gload<float>(a.invh + mr * a.n_panels + j);
+        }
+      };
+      // panel j's table into LDS (all threads; the caller brackets it with barriers)
+      auto load_table = [&](int j) {
+        tab4* tl = (tab4*)(smem + LDS_BYTES + IH_BYTES);
+        const tab4* tg = (const tab4*)a.panels[j].table;
+        for (int k = tid; k < kTabIntervals; k += NT) tl[k] = gload<tab4>(tg + k);
+      };
+      int ih_panel = a.cblocks[ctile * WN].panel;
+      load_rows(ih_panel);
+      if constexpr (LT) {
+        if (ih_panel != tab_panel) {  // the last tile's epilogue ended at the barrier below
+          load_table(ih_panel);
+          tab_panel = ih_panel;
+          __syncthreads();
+        }
+      }
       // projection correction (see gemm_kernel)
 #pragma unroll
       for (int fn = 0; fn < WN; ++fn) {
@@ -1723,20 +1891,55 @@ __global__ __launch_bounds__(NW * 64) void gemm_wide_kernel(GemmArgs a) {
           }
         }
       }
-      float* stage = (float*)smem + wave * (WMF * 32 * 32);
+      // SB column blocks are staged at once (as many as the stages hold), so
+      // that their accumulators are dead before the row loops run
+      constexpr int SB = LDS_BYTES / (NW * WMF * 32 * 32 * 4) < WN ? LDS_BYTES / (NW * WMF * 32 * 32 * 4) : WN;
+      static_assert(SB >= 1 && WN % SB == 0, "staged column blocks");
+      const int wv = __builtin_amdgcn_readfirstlane(wave);  // uniform: LDS bases in scalar registers
+      float* stage = (float*)smem + wv * (SB * WMF * 32 * 32);
 #pragma unroll
-      for (int fn = 0; fn < WN; ++fn) {
-        const int cb = ctile * WN + fn;
-        if (cb >= a.n_cblocks) break;
+      for (int f0 = 0; f0 < WN; f0 += SB) {
+        if (ctile * WN + f0 >= a.n_cblocks) break;
 #pragma unroll
-        for (int fm = 0; fm < WMF; ++fm)
+        for (int s = 0; s < SB; ++s)
 #pragma unroll
-          for (int i = 0; i < 16; ++i)
-            stage[(fm * 32 + 8 * (i >> 2) + 4 * h + (i & 3)) * 32 + r32] = acc[fm][fn][i];
+          for (int fm = 0; fm < WMF; ++fm)
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+              stage[(s * WMF * 32 + fm * 32 + 8 * (i >> 2) + 4 * h + (i & 3)) * 32 + r32] = acc[fm][f0 + s][i];
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        finish_block<WMF>(stage, a, a.cblocks[cb], rowbase, h, r32);
+#pragma unroll
+        for (int s = 0; s < SB; ++s) {
+          const int fn = f0 + s;
+          const int cb = ctile * WN + fn;
+          if (cb >= a.n_cblocks) break;
+          const ColBlock blk = a.cblocks[cb];
+          if (blk.panel != ih_panel) {  // a column tile across a panel boundary
+            ih_panel = blk.panel;
+            load_rows(ih_panel);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          }
+          if constexpr (LT) {
+            if (blk.panel != tab_panel) {
+              __syncthreads();
+              load_table(blk.panel);
+              tab_panel = blk.panel;
+              __syncthreads();
+            }
+          }
+          const float* sb = stage + s * (WMF * 32 * 32);
+          const LdsRows ihr = (LdsRows)ihl;
+          if constexpr (LT)
+            finish_block<WMF>(sb, a, blk, rowbase, h, r32, (LdsTable)(smem + LDS_BYTES + IH_BYTES), ihr, cinv[fn],
+                              csp[fn]);
+          else
+            finish_block<WMF>(sb, a, blk, rowbase, h, r32, (const tab4*)a.panels[blk.panel].table, ihr, cinv[fn],
+                              csp[fn]);
+        }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -1890,8 +2093,8 @@ hipError_t launch_set_operand(const float* V, int64_t ldv, int64_t n, int64_t n_
   return hipGetLastError();
 }
 
-hipError_t launch_table(float2* table, double df, hipStream_t s) {
-  hipLaunchKernelGGL(table_kernel, dim3((kTabNodes + 255) / 256), dim3(256), 0, s, table, df);
+hipError_t launch_table(float4* table, double df, hipStream_t s) {
+  hipLaunchKernelGGL(table_kernel, dim3((kTabIntervals + 255) / 256), dim3(256), 0, s, table, df);
   return hipGetLastError();
 }
 

@@ -94,7 +94,7 @@ struct tgw_panel {
   float* scale = nullptr;
   float* invny = nullptr;
   float* cw = nullptr;
-  float2* table = nullptr;
+  float4* table = nullptr;
   uint8_t* lscale = nullptr;  // FP8 lo form: E8M0 scale per column
 };
 
@@ -294,7 +294,7 @@ extern "C" tgw_status tgw_prepare_phenotypes(const tgw_covariates* cov, int64_t 
   if (e == hipSuccess) e = dmalloc(&p->scale, p->P_pad);
   if (e == hipSuccess) e = dmalloc(&p->invny, p->P_pad);
   if (e == hipSuccess) e = dmalloc(&p->cw, (size_t)p->P_pad * kSlots);
-  if (e == hipSuccess) e = dmalloc(&p->table, kTabNodes);
+  if (e == hipSuccess) e = dmalloc(&p->table, kTabIntervals);
   if (e == hipSuccess) e = dmalloc(&flags, 1);
   if (e == hipSuccess) e = hipMemsetAsync(p->yop, 0, op_bytes, s);
   if (e == hipSuccess) e = hipMemsetAsync(p->scale, 0, p->P_pad * sizeof(float), s);
@@ -571,6 +571,7 @@ tgw_status tgw::check_call(const tgw_plan* pl, const ScanCall& c, bool need_outs
       const tgw_outputs& o = c.outs[j];
       const bool dense = o.r || o.beta || o.se || o.t || o.nlog10p;
       if (dense && o.ld < pl->panels[j]->P) return fail(TGW_ERR_SHAPE, "outs[j].ld < n_pheno of panel j");
+      if (dense && o.ld > kMaxOutLd) return fail(TGW_ERR_SHAPE, "outs[j].ld above 2^22 elements");
       if (o.best && c.m_end > 0xffffffffll) return fail(TGW_ERR_SHAPE, "best needs marker indices below 2^32");
     }
   }

@@ -280,6 +280,10 @@ def test_errors(tgw):
         plan.scan(torch.zeros((10, 16), dtype=torch.uint8, device="cuda"), outs)
     assert e.value.status == tgw.ERR_SHAPE  # row too short for n = 100
     plan.scan(g, outs, 3, 3)  # empty range is a no-op
+    wide = torch.empty((1, (1 << 22) + 1), dtype=torch.float32, device="cuda")[:, :4]
+    with pytest.raises(tgw.TgwError) as e:
+        plan.scan(g, [{"r": wide}], 0, 1)  # output row stride above 2^22 elements
+    assert e.value.status == tgw.ERR_SHAPE
 
 
 # ---------------------------------------------------------------------------
@@ -348,6 +352,31 @@ def test_batching_equals_single(tgw):
                                torch.nan_to_num(outs_all[j][k], nan=7.0)), (j, k)
         ref = oracle_scan(codes, Cs[j] if Cs[j].shape[1] else None, Ys[j])
         compare({k: v.cpu().numpy() for k, v in outs_all[j].items()}, ref, ref["df"], f"batch panel {j} ")
+
+
+@pytest.mark.parametrize("precision,tile", [("split8", 1), ("split8", 0), ("split8", 6), ("split", 1)])
+def test_batching_wide_tiles(tgw, precision, tile):
+    """Column tiles that straddle panels of different K (so different degrees
+    of freedom and p-value tables) in each wide tile shape: the epilogue
+    switches its per-row values and table copy between column blocks."""
+    spec = cohort_spec("cfg1")
+    say(f"case: batching across panels {precision} tile={tile}")
+    rng = np.random.default_rng(78)
+    codes, packed, _, _ = cohort_arrays(spec, np.arange(1100))
+    n = spec.n_samples
+    sizes = [(20, 2), (70, 5), (5, 0), (33, 9), (150, 1)]
+    Cs, Ys = [], []
+    for p, k in sizes:
+        Cs.append(rng.standard_normal((n, k)))
+        Ys.append((rng.standard_normal((n, p))
+                   + (Cs[-1] @ rng.standard_normal((k, p)) if k else 0.0)).astype(np.float32))
+    g = torch.from_numpy(packed).cuda()
+    covs = [tgw.fit_covariates(torch.from_numpy(Cc).cuda() if Cc.shape[1] else None, n_samples=n) for Cc in Cs]
+    panels = [tgw.prepare_phenotypes(cv, torch.from_numpy(Yy).cuda(), precision) for cv, Yy in zip(covs, Ys)]
+    outs = tgw.scan(tgw.Plan(panels, tile=tile), g)
+    for j in range(len(sizes)):
+        ref = oracle_scan(codes, Cs[j] if Cs[j].shape[1] else None, Ys[j])
+        compare({k: v.cpu().numpy() for k, v in outs[j].items()}, ref, ref["df"], f"{precision} tile {tile} panel {j} ")
 
 
 # ---------------------------------------------------------------------------
