@@ -772,6 +772,28 @@ __global__ void tail_kernel(TailDev t, const PanelDev* __restrict__ panels, cons
   }
 }
 
+// Tile order of the wide kernel: super-tiles of kGroupM marker tiles x
+// kGroupC column tiles, walked column group by column group, marker group by
+// marker group; within a super-tile, column tile fastest.  An XCD's 32
+// workgroups then run on about one super-tile at a time, so a genotype chunk
+// is fetched once for kGroupC workgroups and an operand chunk once for
+// kGroupM (column-tile-major order fetches the genotypes once per column
+// tile).  w in [0, n_mtiles * n_ctiles) maps one to one; edge groups are
+// ragged.
+constexpr int kGroupM = 8, kGroupC = 4;
+__device__ __forceinline__ void grouped_tile(int64_t w, int nm, int nc, int& mtile, int& ctile) {
+  const int64_t full = (int64_t)nm * kGroupC;  // tiles of a full column group
+  const int cg = (int)(w / full);
+  const int64_t u = w - (int64_t)cg * full;
+  const int c = nc - cg * kGroupC < kGroupC ? nc - cg * kGroupC : kGroupC;
+  const int64_t sg = (int64_t)kGroupM * c;  // tiles of a full marker group in this column group
+  const int mg = (int)(u / sg);
+  const int r = (int)(u - (int64_t)mg * sg);
+  const int mi = r / c;
+  mtile = mg * kGroupM + mi;
+  ctile = cg * kGroupC + (r - mi * c);
+}
+
 // ---------------------------------------------------------------------------
 // the contraction (Eq. 2) with the fused epilogue
 //
@@ -1419,8 +1441,8 @@ __global__ __launch_bounds__(NW * 64) void gemm_wide_kernel(GemmArgs a) {
   const int64_t whi = W * (xcd + 1) / 8;
 
   for (int64_t w = wlo + slot; w < whi; w += nslots) {
-    const int ctile = (int)(w / a.n_mtiles);
-    const int mtile = (int)(w - (int64_t)ctile * a.n_mtiles);
+    int mtile, ctile;
+    grouped_tile(w, a.n_mtiles, a.n_ctiles, mtile, ctile);
     const char* bop[WN];
     int bscale[WN];  // FP8 form: E8M0 scale of this lane's column, per block
 #pragma unroll
