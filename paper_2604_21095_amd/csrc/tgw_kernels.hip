@@ -772,14 +772,14 @@ __global__ void tail_kernel(TailDev t, const PanelDev* __restrict__ panels, cons
   }
 }
 
-// Tile order of the wide kernel: super-tiles of kGroupM marker tiles x
-// kGroupC column tiles, walked column group by column group, marker group by
-// marker group; within a super-tile, column tile fastest.  An XCD's 32
-// workgroups then run on about one super-tile at a time, so a genotype chunk
-// is fetched once for kGroupC workgroups and an operand chunk once for
-// kGroupM (column-tile-major order fetches the genotypes once per column
-// tile).  w in [0, n_mtiles * n_ctiles) maps one to one; edge groups are
-// ragged.
+// Tile order of the persistent kernels: super-tiles of kGroupM marker tiles
+// x kGroupC column tiles, walked column group by column group, marker group
+// by marker group; within a super-tile, column tile fastest.  The 32
+// workgroups an XCD runs at once (wide kernel) then work on about one
+// super-tile, so a genotype chunk is fetched once for kGroupC workgroups and
+// an operand chunk once for kGroupM (column-tile-major order fetches the
+// genotypes once per column tile).  w in [0, n_mtiles * n_ctiles) maps one
+// to one; edge groups are ragged.
 constexpr int kGroupM = 8, kGroupC = 4;
 __device__ __forceinline__ void grouped_tile(int64_t w, int nm, int nc, int& mtile, int& ctile) {
   const int64_t full = (int64_t)nm * kGroupC;  // tiles of a full column group
@@ -1089,8 +1089,8 @@ __global__ __launch_bounds__(NW * 64) void gemm_kernel(GemmArgs a) {
   const int64_t whi = W * (xcd + 1) / 8;
 
   for (int64_t w = wlo + slot; w < whi; w += nslots) {
-    const int ctile = (int)(w / a.n_mtiles);
-    const int mtile = (int)(w - (int64_t)ctile * a.n_mtiles);
+    int mtile, ctile;
+    grouped_tile(w, a.n_mtiles, a.n_ctiles, mtile, ctile);
 
     // operand blocks of this column tile; blocks past the end alias the
     // first one (their columns are never written)
