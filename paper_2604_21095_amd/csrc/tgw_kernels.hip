@@ -420,112 +420,187 @@ __global__ void cov_operand_kernel(const double* __restrict__ Q, int64_t n, int6
 }
 
 // ---------------------------------------------------------------------------
-// phenotype preparation, one workgroup per column (Eq. 1 + standardization)
+// phenotype preparation (Eq. 1 + standardization): one workgroup per CPW
+// columns, so that each element of Q read from L2 serves CPW columns; QS >= q
+// slots of the projections are kept per column.  Every column's arithmetic
+// and summation order is that of a workgroup running it alone.
 // ---------------------------------------------------------------------------
 constexpr int kPrepThreads = 256;
 
+template <int QS, int CPW>
 __global__ __launch_bounds__(kPrepThreads) void prep_kernel(const void* __restrict__ Y, int y_fp64, int64_t ldy,
                                                             int64_t n, int64_t n_pad, int64_t P,
                                                             const double* __restrict__ Q, int q, int prec,
                                                             void* yop, float* scale, float* invny, float* cw,
                                                             uint8_t* lscale, int32_t* flags) {
-  __shared__ double sh[(kPrepThreads / 64) * (kSlots + 2)];
-  __shared__ double qty_s[kSlots];
-  const int64_t p = blockIdx.x;
+  static_assert(QS <= kSlots, "projection slots");
+  constexpr int NV = CPW * (QS + 2);
+  __shared__ double sh[(kPrepThreads / 64) * NV];
+  __shared__ double qty_s[CPW][QS];
   const int tid = threadIdx.x;
   const int n_chunks = (int)(n_pad / kChunk);
-  const float* yf = (const float*)Y + p * ldy;
-  const double* yd = (const double*)Y + p * ldy;
-  auto yval = [&](int64_t i) -> double { return y_fp64 ? yd[i] : (double)yf[i]; };
+  const int64_t p0 = (int64_t)blockIdx.x * CPW;
+  // columns past P repeat the last one; nothing of theirs is stored
+  int64_t pc[CPW];
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) pc[c] = p0 + c < P ? p0 + c : P - 1;
+  auto yval = [&](int c, int64_t i) -> double {
+    return y_fp64 ? ((const double*)Y)[pc[c] * ldy + i] : (double)((const float*)Y)[pc[c] * ldy + i];
+  };
+  auto load_q = [&](int64_t i, double* qv) {
+#pragma unroll
+    for (int k = 0; k < QS; ++k) qv[k] = k < q ? Q[(int64_t)k * n_pad + i] : 0.0;
+  };
 
-  // pass 1: mean (and finiteness)
-  double s = 0.0;
+  // pass 1: means (and finiteness)
+  double mean[CPW];
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) mean[c] = 0.0;
   int bad = 0;
   for (int64_t i = tid; i < n; i += kPrepThreads) {
-    const double v = yval(i);
-    if (!isfinite(v)) bad = 1;
-    s += v;
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      const double v = yval(c, i);
+      if (!isfinite(v)) bad = 1;
+      mean[c] += v;
+    }
   }
   bad = __syncthreads_or(bad);
   if (bad) {
     if (tid == 0) atomicOr(flags, 1);
     return;
   }
-  const double mean = block_sum<kPrepThreads>(s, sh) / (double)n;
+  block_sum_vec<kPrepThreads, CPW>(mean, sh);
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) mean[c] /= (double)n;
 
-  // pass 2: Q^T y_c and ||y_c||^2
-  double acc[kSlots + 2];
+  // pass 2: Q^T y_c and ||y_c||^2 (slot QS)
+  double acc[CPW][QS + 2];
 #pragma unroll
-  for (int k = 0; k < kSlots + 2; ++k) acc[k] = 0.0;
+  for (int c = 0; c < CPW; ++c)
+#pragma unroll
+    for (int k = 0; k < QS + 2; ++k) acc[c][k] = 0.0;
   for (int64_t i = tid; i < n; i += kPrepThreads) {
-    const double yc = yval(i) - mean;
-    acc[kSlots] += yc * yc;
+    double qv[QS];
+    load_q(i, qv);
 #pragma unroll
-    for (int k = 0; k < kSlots; ++k)
-      if (k < q) acc[k] += Q[(int64_t)k * n_pad + i] * yc;
+    for (int c = 0; c < CPW; ++c) {
+      const double yc = yval(c, i) - mean[c];
+      acc[c][QS] += yc * yc;
+#pragma unroll
+      for (int k = 0; k < QS; ++k)
+        if (k < q) acc[c][k] += qv[k] * yc;
+    }
   }
-  block_sum_vec<kPrepThreads, kSlots + 2>(acc, sh);
-  const double yc2 = acc[kSlots];
-  if (tid < kSlots) qty_s[tid] = acc[tid];
+  block_sum_vec<kPrepThreads, NV>(&acc[0][0], sh);
+  double yc2[CPW];
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    yc2[c] = acc[c][QS];
+#pragma unroll
+    for (int k = 0; k < QS; ++k)
+      if (tid == k) qty_s[c][k] = acc[c][k];
+  }
   __syncthreads();
 
-  // pass 3: ||y_res||^2
-  double r2 = 0.0;
-  for (int64_t i = tid; i < n; i += kPrepThreads) {
-    double v = yval(i) - mean;
-    for (int k = 0; k < q; ++k) v -= Q[(int64_t)k * n_pad + i] * qty_s[k];
-    r2 += v * v;
-  }
-  r2 = block_sum<kPrepThreads>(r2, sh);
-  const double sp = sqrt(r2);
-  const bool valid = sp > 1e-12 * sqrt(yc2);
-  const double inv = valid ? 1.0 / sp : 0.0;
+  // y_res of column c at sample i, given Q's column i
+  auto yres = [&](int c, int64_t i, const double* qv) {
+    double v = yval(c, i) - mean[c];
+#pragma unroll
+    for (int k = 0; k < QS; ++k)
+      if (k < q) v -= qv[k] * qty_s[c][k];
+    return v;
+  };
 
-  // pass 3b (FP8 lo form): the column's largest lo term sets its scale
-  int lsh = 0;
-  if (prec == kSplit8) {
-    double mx = 0.0;
-    for (int64_t i = tid; i < n; i += kPrepThreads) {
-      double v = yval(i) - mean;
-      for (int k = 0; k < q; ++k) v -= Q[(int64_t)k * n_pad + i] * qty_s[k];
-      const double vs = v * inv * (double)kF16Scale;
-      mx = fmax(mx, fabs(vs - (double)f16_to_float(f16_bits_rn((float)vs))));
+  // pass 3: ||y_res||^2
+  double r2[CPW];
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) r2[c] = 0.0;
+  for (int64_t i = tid; i < n; i += kPrepThreads) {
+    double qv[QS];
+    load_q(i, qv);
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      const double v = yres(c, i, qv);
+      r2[c] += v * v;
     }
-    mx = block_max<kPrepThreads>(mx, sh);
-    lsh = lo_shift(mx);
-    if (tid == 0) lscale[p] = (uint8_t)(127 - lsh);
+  }
+  block_sum_vec<kPrepThreads, CPW>(r2, sh);
+  double sp[CPW], inv[CPW];
+  bool valid[CPW];
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    sp[c] = sqrt(r2[c]);
+    valid[c] = sp[c] > 1e-12 * sqrt(yc2[c]);
+    inv[c] = valid[c] ? 1.0 / sp[c] : 0.0;
+  }
+
+  // pass 3b (FP8 lo form): each column's largest lo term sets its scale
+  int lsh[CPW];
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) lsh[c] = 0;
+  if (prec == kSplit8) {
+    double mx[CPW];
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) mx[c] = 0.0;
+    for (int64_t i = tid; i < n; i += kPrepThreads) {
+      double qv[QS];
+      load_q(i, qv);
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) {
+        const double vs = yres(c, i, qv) * inv[c] * (double)kF16Scale;
+        mx[c] = fmax(mx[c], fabs(vs - (double)f16_to_float(f16_bits_rn((float)vs))));
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      lsh[c] = lo_shift(block_max<kPrepThreads>(mx[c], sh));
+      if (tid == 0 && p0 + c < P) lscale[p0 + c] = (uint8_t)(127 - lsh[c]);
+    }
   }
 
   // pass 4: y~ = y_res / s_p into the operand; accumulate what the stored
-  // (rounded) operand actually holds: sum, norm^2 and Q^T y_op
+  // (rounded) operand actually holds: Q^T y_op, sum (slot QS), norm^2 (QS + 1)
 #pragma unroll
-  for (int k = 0; k < kSlots + 2; ++k) acc[k] = 0.0;
+  for (int c = 0; c < CPW; ++c)
+#pragma unroll
+    for (int k = 0; k < QS + 2; ++k) acc[c][k] = 0.0;
   for (int64_t i = tid; i < n; i += kPrepThreads) {
-    double v = yval(i) - mean;
-    for (int k = 0; k < q; ++k) v -= Q[(int64_t)k * n_pad + i] * qty_s[k];
-    double st;
-    store_operand(yop, prec, p, i, n_chunks, v * inv, &st, lsh);
-    acc[kSlots] += st;
-    acc[kSlots + 1] += st * st;
+    double qv[QS];
+    load_q(i, qv);
 #pragma unroll
-    for (int k = 0; k < kSlots; ++k)
-      if (k < q) acc[k] += Q[(int64_t)k * n_pad + i] * st;
+    for (int c = 0; c < CPW; ++c) {
+      if (p0 + c >= P) continue;
+      double st;
+      store_operand(yop, prec, p0 + c, i, n_chunks, yres(c, i, qv) * inv[c], &st, lsh[c]);
+      acc[c][QS] += st;
+      acc[c][QS + 1] += st * st;
+#pragma unroll
+      for (int k = 0; k < QS; ++k)
+        if (k < q) acc[c][k] += qv[k] * st;
+    }
   }
-  block_sum_vec<kPrepThreads, kSlots + 2>(acc, sh);
-  if (tid == 0) {
-    double proj = 0.0;
-    for (int k = 0; k < q; ++k) proj += acc[k] * acc[k];
-    const double ny2 = acc[kSlots + 1] - proj;
-    scale[p] = (float)sp;
-    invny[p] = (valid && ny2 > 0.0) ? (float)(1.0 / sqrt(ny2)) : __builtin_nanf("");
-  }
-  if (tid < kSlots) {
-    float v = 0.0f;
-    if (tid == 0)
-      v = (float)(-acc[kSlots]);
-    else if (tid < q)
-      v = (float)(-acc[tid]);
-    cw[p * kSlots + tid] = v;
+  block_sum_vec<kPrepThreads, NV>(&acc[0][0], sh);
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    const int64_t p = p0 + c;
+    if (p >= P) break;
+    if (tid == 0) {
+      double proj = 0.0;
+#pragma unroll
+      for (int k = 0; k < QS; ++k)
+        if (k < q) proj += acc[c][k] * acc[c][k];
+      const double ny2 = acc[c][QS + 1] - proj;
+      scale[p] = (float)sp[c];
+      invny[p] = (valid[c] && ny2 > 0.0) ? (float)(1.0 / sqrt(ny2)) : __builtin_nanf("");
+    }
+    if (tid < kSlots) {
+      float v = tid == 0 ? (float)(-acc[c][QS]) : 0.0f;
+#pragma unroll
+      for (int k = 1; k < QS; ++k)
+        if (tid == k && k < q) v = (float)(-acc[c][k]);
+      cw[p * kSlots + tid] = v;
+    }
   }
 }
 
@@ -621,28 +696,35 @@ __global__ __launch_bounds__(256) void stats_kernel(StatsArgs a) {
     stats_dosage8(a, m, lane);
     return;
   }
-  const uint32_t* row = (const uint32_t*)(a.geno + (a.m0 + m) * a.row_bytes);
-  const int64_t nd = (a.n + 15) / 16;
+  // 16 bytes (64 samples) per lane and load; rows are 16-byte aligned and
+  // hold at least ceil(n / 64) such pieces
+  const uint4* row = (const uint4*)(a.geno + (a.m0 + m) * a.row_bytes);
+  const int64_t n16 = (a.n + 63) / 64;
   int nmiss = 0, c1 = 0, c2 = 0;
-  for (int64_t d = lane; d < nd; d += 64) {
-    const uint32_t w = row[d];
-    const int64_t nv = a.n - 16 * d;
-    const uint32_t vm = nv >= 16 ? 0xffffffffu : ((1u << (2 * nv)) - 1u);
-    const uint32_t lo = w & 0x55555555u & vm;
-    const uint32_t hi = (w >> 1) & 0x55555555u & vm;
-    uint32_t miss, one, two;
-    if (a.code == 0) {  // dosage: 0,1,2, 3 = missing
-      miss = lo & hi;
-      one = lo & ~hi;
-      two = hi & ~lo;
-    } else {  // PLINK .bed: 0 -> 0, 1 -> missing, 2 -> 1, 3 -> 2
-      miss = lo & ~hi;
-      one = hi & ~lo;
-      two = lo & hi;
+  for (int64_t d4 = lane; d4 < n16; d4 += 64) {
+    const uint4 w4 = row[d4];
+    const uint32_t ws[4] = {w4.x, w4.y, w4.z, w4.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint32_t w = ws[q];
+      const int64_t nv = a.n - 16 * (4 * d4 + q);  // samples in this word
+      const uint32_t vm = nv >= 16 ? 0xffffffffu : (nv <= 0 ? 0u : ((1u << (2 * nv)) - 1u));
+      const uint32_t lo = w & 0x55555555u & vm;
+      const uint32_t hi = (w >> 1) & 0x55555555u & vm;
+      uint32_t miss, one, two;
+      if (a.code == 0) {  // dosage: 0,1,2, 3 = missing
+        miss = lo & hi;
+        one = lo & ~hi;
+        two = hi & ~lo;
+      } else {  // PLINK .bed: 0 -> 0, 1 -> missing, 2 -> 1, 3 -> 2
+        miss = lo & ~hi;
+        one = hi & ~lo;
+        two = lo & hi;
+      }
+      nmiss += __popc(miss);
+      c1 += __popc(one);
+      c2 += __popc(two);
     }
-    nmiss += __popc(miss);
-    c1 += __popc(one);
-    c2 += __popc(two);
   }
   for (int o = 32; o > 0; o >>= 1) {
     nmiss += __shfl_xor(nmiss, o);
@@ -2098,8 +2180,23 @@ hipError_t launch_cov_operands(const double* Q, int64_t n, int64_t n_pad, int q,
 hipError_t launch_prep(const void* Y, int y_fp64, int64_t ldy, int64_t n, int64_t n_pad, int64_t P,
                        const double* Q, int q, int prec, void* yop, float* scale, float* invny, float* cw,
                        uint8_t* lscale, int32_t* flags, hipStream_t s) {
-  hipLaunchKernelGGL(prep_kernel, dim3((unsigned)P), dim3(kPrepThreads), 0, s, Y, y_fp64, ldy, n, n_pad, P, Q,
-                     q, prec, yop, scale, invny, cw, lscale, flags);
+  // q <= QS slots; as many columns per workgroup as registers allow
+  auto go = [&](auto kern, int cpw) {
+    hipLaunchKernelGGL(kern, dim3((unsigned)((P + cpw - 1) / cpw)), dim3(kPrepThreads), 0, s, Y, y_fp64, ldy, n,
+                       n_pad, P, Q, q, prec, yop, scale, invny, cw, lscale, flags);
+  };
+  if (q <= 4)
+    go(prep_kernel<4, 4>, 4);
+  else if (q <= 8)
+    go(prep_kernel<8, 4>, 4);
+  else if (q <= 12)
+    go(prep_kernel<12, 4>, 4);
+  else if (q <= 16)
+    go(prep_kernel<16, 2>, 2);
+  else if (q <= 24)
+    go(prep_kernel<24, 2>, 2);
+  else
+    go(prep_kernel<kSlots, 1>, 1);
   return hipGetLastError();
 }
 
