@@ -56,9 +56,9 @@ WIDE_TILES = (0, 1, 6)  # persistent LDS-ring kernel shapes (the split forms onl
 
 def load_traffic(workload: str, precision: str, tile: int):
     """HBM bytes per main-kernel launch measured with rocprofv3 counters
-    (profiles/traffic_gemm_<precision>_<workload>.txt, "key: value" lines), if
-    the kernel source and tile shape have not changed since they were taken."""
-    path = os.path.join(ROOT, "profiles", f"traffic_gemm_{precision}_{workload}.txt")
+    (profiles/traffic_gemm_<precision>_<workload>_tile<tile>.txt, "key: value"
+    lines), if the kernel source has not changed since they were taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_gemm_{precision}_{workload}_tile{tile}.txt")
     if not os.path.exists(path):
         return None
     d = {}
