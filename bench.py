@@ -422,8 +422,9 @@ def main():
         return
 
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the scan shards by phenotype "
-              "columns across GPUs without collectives, see DESIGN.md", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); across GPUs the scan would shard "
+              "by phenotype columns (each GPU a column range of every panel, the genotype stream replicated), "
+              "which needs no collectives", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
