@@ -347,49 +347,79 @@ __global__ __launch_bounds__(kQrThreads) void qr_kernel(const double* __restrict
     if (tid == 0) flags[0] = 1;
     return;
   }
+  // Householder step j: passes over the rows below j gather ||x_j||^2 and
+  // x_j . x_k for the later columns k, CB columns a pass (their sums are
+  // reduced together); one pass then applies the reflection to all of them
+  constexpr int NQ = kMaxCov + 1, CB = 4;
+  __shared__ double shv[(kQrThreads / 64) * CB];
+  __shared__ double dv_s[NQ];
+  __shared__ double f_s[NQ];
+  // dv_s[k] = sum over rows i >= i0 of v[i] * W[k][i], for j0 <= k < q
+  auto dots = [&](const double* v, const double* W, int j0, int64_t i0) {
+    for (int k0 = j0; k0 < q; k0 += CB) {
+      double d[CB];
+#pragma unroll
+      for (int t = 0; t < CB; ++t) d[t] = 0.0;
+#pragma unroll 1
+      for (int64_t i = i0 + tid; i < n; i += kQrThreads) {
+        const double vi = v[i];
+#pragma unroll
+        for (int t = 0; t < CB; ++t)
+          if (k0 + t < q) d[t] += vi * W[(int64_t)(k0 + t) * n_pad + i];
+      }
+      block_sum_vec<kQrThreads, CB>(d, shv);
+      if (tid == 0) {
+#pragma unroll
+        for (int t = 0; t < CB; ++t)
+          if (k0 + t < q) dv_s[k0 + t] = d[t];
+      }
+    }
+    __syncthreads();
+  };
   for (int j = 0; j < q; ++j) {
     double* xj = X + (int64_t)j * n_pad;
-    double s = 0.0;
-    for (int64_t i = j + tid; i < n; i += kQrThreads) s += xj[i] * xj[i];
-    s = block_sum<kQrThreads>(s, sh);
-    const double xjj = xj[j];
-    const double nrm = sqrt(s);
-    const double alpha = xjj > 0.0 ? -nrm : nrm;
-    const double v0 = xjj - alpha;
-    const double vtv = s - xjj * xjj + v0 * v0;
-    __syncthreads();
+    dots(xj, X, j, j + 1);  // dv_s[j]: squares below row j; dv_s[k > j]: dots below row j
     if (tid == 0) {
+      const double xjj = xj[j];
+      const double below = dv_s[j];
+      const double nrm = sqrt(xjj * xjj + below);
+      const double alpha = xjj > 0.0 ? -nrm : nrm;
+      const double v0 = xjj - alpha;
+      const double vtv = below + v0 * v0;
       xj[j] = v0;
       rdiag[j] = alpha;
       vtv_s[j] = vtv;
+      for (int k = j + 1; k < q; ++k)
+        f_s[k] = vtv > 0.0 ? 2.0 * (dv_s[k] + v0 * X[(int64_t)k * n_pad + j]) / vtv : 0.0;
     }
     __syncthreads();
-    for (int k = j + 1; k < q; ++k) {
-      double* xk = X + (int64_t)k * n_pad;
-      double d = 0.0;
-      for (int64_t i = j + tid; i < n; i += kQrThreads) d += xj[i] * xk[i];
-      d = block_sum<kQrThreads>(d, sh);
-      const double f = vtv > 0.0 ? 2.0 * d / vtv : 0.0;
-      for (int64_t i = j + tid; i < n; i += kQrThreads) xk[i] -= f * xj[i];
-      __syncthreads();
+#pragma unroll 1
+    for (int64_t i = j + tid; i < n; i += kQrThreads) {
+      const double vi = xj[i];
+#pragma unroll 1
+      for (int k = j + 1; k < q; ++k) X[(int64_t)k * n_pad + i] -= f_s[k] * vi;
     }
+    __syncthreads();
   }
-  // Q = H_0 ... H_{q-1} [I_q; 0]
+  // Q = H_0 ... H_{q-1} [I_q; 0], the reflections applied from the last
   for (int k = 0; k < q; ++k)
     for (int64_t i = tid; i < n_pad; i += kQrThreads) Q[(int64_t)k * n_pad + i] = (i == k) ? 1.0 : 0.0;
   __syncthreads();
   for (int j = q - 1; j >= 0; --j) {
     const double* xj = X + (int64_t)j * n_pad;
-    const double vtv = vtv_s[j];
-    for (int k = j; k < q; ++k) {
-      double* qk = Q + (int64_t)k * n_pad;
-      double d = 0.0;
-      for (int64_t i = j + tid; i < n; i += kQrThreads) d += xj[i] * qk[i];
-      d = block_sum<kQrThreads>(d, sh);
-      const double f = vtv > 0.0 ? 2.0 * d / vtv : 0.0;
-      for (int64_t i = j + tid; i < n; i += kQrThreads) qk[i] -= f * xj[i];
-      __syncthreads();
+    dots(xj, Q, j, j);
+    if (tid == 0) {
+      const double vtv = vtv_s[j];
+      for (int k = j; k < q; ++k) f_s[k] = vtv > 0.0 ? 2.0 * dv_s[k] / vtv : 0.0;
     }
+    __syncthreads();
+#pragma unroll 1
+    for (int64_t i = j + tid; i < n; i += kQrThreads) {
+      const double vi = xj[i];
+#pragma unroll 1
+      for (int k = j; k < q; ++k) Q[(int64_t)k * n_pad + i] -= f_s[k] * vi;
+    }
+    __syncthreads();
   }
   if (tid == 0) {
     double mx = 0.0;
