@@ -1502,9 +1502,13 @@ constexpr int waitcnt_vm_lgkm0(int vm) { return (vm & 15) | ((vm >> 4) << 14) | 
 // vmcnt(vm) only (expcnt and lgkmcnt unconstrained)
 constexpr int waitcnt_vm_only(int vm) { return waitcnt_vm_lgkm0(vm) | (0xF << 8); }
 
-template <int PREC, int MODE, int NW, int WMF, int WN = 4>
+// G8: 8-bit dosage rows (FP16 split only): each stage holds the tile's 64
+// bytes per marker; a lane reads the two dwords of its row that each K16 step
+// needs and builds FP16 q - c as the register-staged kernel does.
+template <int PREC, int MODE, int NW, int WMF, int WN = 4, bool G8 = false>
 __global__ __launch_bounds__(NW * 64) void gemm_wide_kernel(GemmArgs a) {
   static_assert(PREC != kFP32, "the wide kernel runs the split forms");
+  static_assert(!G8 || PREC == kSplit16, "8-bit dosages run the FP16 split form here");
   static_assert((NW * WMF == 16 && WN == 4 && (WMF == 4 || WMF == 2)) ||
                     (NW == 4 && WMF == 2 && WN == 8 && PREC == kSplit8),
                 "512 x 128 tiles, or 256 x 256 for the FP8 lo form");
@@ -1514,9 +1518,10 @@ __global__ __launch_bounds__(NW * 64) void gemm_wide_kernel(GemmArgs a) {
   constexpr int NT = NW * 64;
   constexpr int TM = NW * WMF * 32;
   constexpr int BB = block_bytes(PREC);
-  constexpr int NSTAGE = F8 ? (WN == 8 ? 3 : 4) : 3;
+  constexpr int NSTAGE = F8 ? (WN == 8 ? 3 : 4) : (G8 ? 2 : 3);
   constexpr int B_BYTES = WN * BB;  // operand chunk of the column tile
-  constexpr int A_BYTES = TM * 16;  // 64 two-bit codes of each marker
+  constexpr int AB = G8 ? 64 : 16;  // bytes of a marker's chunk: 64 two-bit codes or 64 dosage bytes
+  constexpr int A_BYTES = TM * AB;
   constexpr int STAGE_BYTES = B_BYTES + A_BYTES;
   constexpr int LDS_BYTES = NSTAGE * STAGE_BYTES;
   constexpr int PPB = BB / 1024;                // 1 KiB pieces per operand block
@@ -1585,12 +1590,15 @@ __global__ __launch_bounds__(NW * 64) void gemm_wide_kernel(GemmArgs a) {
     }
     // code rows copied by this lane: markers rowbase + 64 k + lane (rows
     // past the end read the last row; their results are never stored)
+    // (8-bit dosages: 16-byte piece 64 k + lane of the wave's rows, i.e.
+    // quarter (64 k + lane) & 3 of marker rowbase + (64 k + lane) / 4)
     const uint8_t* arow[A_OPS];
 #pragma unroll
     for (int k = 0; k < A_OPS; ++k) {
-      int64_t mr = rowbase + 64 * k + lane;
+      const int piece = 64 * k + lane;
+      int64_t mr = rowbase + (G8 ? piece >> 2 : piece);
       mr = mr < a.nm ? mr : a.nm - 1;
-      arow[k] = a.geno + (a.m0 + mr) * a.row_bytes;
+      arow[k] = a.geno + (a.m0 + mr) * a.row_bytes + (G8 ? (piece & 3) * 16 : 0);
     }
 
     f32x16 acc[WMF][WN];
@@ -1619,8 +1627,8 @@ __global__ __launch_bounds__(NW * 64) void gemm_wide_kernel(GemmArgs a) {
 #pragma unroll
       for (int k = 0; k < A_OPS; ++k)
         __builtin_amdgcn_global_load_lds(
-            (const __attribute__((address_space(1))) void*)(arow[k] + (int64_t)ch * 16),
-            (__attribute__((address_space(3))) void*)(stage + B_BYTES + wave * (WMF * 32 * 16) + k * 1024), 16, 0,
+            (const __attribute__((address_space(1))) void*)(arow[k] + (int64_t)ch * AB),
+            (__attribute__((address_space(3))) void*)(stage + B_BYTES + wave * (WMF * 32 * AB) + k * 1024), 16, 0,
             0);
     };
     // whole 16-byte rows, this lane's half picked in registers (paired
@@ -1639,6 +1647,36 @@ __global__ __launch_bounds__(NW * 64) void gemm_wide_kernel(GemmArgs a) {
       u32x4 raw[WMF];
       read_a_raw(st, raw);
       pick_a(raw, dst);
+    };
+    // 8-bit dosages: dwords k0 and k0 + 2 (k0 = 4 (j >> 1) + (j & 1)) of this
+    // lane half's 32 bytes of each fragment row, the two that K16 step j needs
+    auto read_g8 = [&](int st, int j, uint2* dst) {
+      const char* ab = smem + st * STAGE_BYTES + B_BYTES + wave * (WMF * 32 * 64) + h * 32;
+      const int k0 = 4 * (j >> 1) + (j & 1);
+#pragma unroll
+      for (int fm = 0; fm < WMF; ++fm) {
+        const char* row = ab + (fm * 32 + r32) * 64;
+        dst[fm] = make_uint2(*(const uint32_t*)(row + 4 * k0), *(const uint32_t*)(row + 4 * (k0 + 2)));
+      }
+    };
+    // slots (2d, 2d + 1) of step j take samples 16 (j >> 1) + 4 (j & 1) + d and
+    // that + 8 of this lane half: byte d of the two dwords read above; FP16
+    // q - c by inserting the byte under the exponent of 1024, a missing byte
+    // takes mu - c
+    auto decode_g8 = [&](const uint2* D, u32x4* A) {
+#pragma unroll
+      for (int fm = 0; fm < WMF; ++fm) {
+        const uint32_t D0 = D[fm].x, D1 = D[fm].y;
+        const uint32_t M0 = ff_bytes(D0), M1 = ff_bytes(D1);
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+          const uint32_t x = __builtin_amdgcn_perm(D1, D0, 0x0c000c00u | ((4u + d) << 16) | d) | 0x64006400u;
+          const uint32_t v =
+              __builtin_bit_cast(uint32_t, __builtin_bit_cast(f16x2, x) + __builtin_bit_cast(f16x2, lut[fm].x));
+          const uint32_t mk = __builtin_amdgcn_perm(M1, M0, d | (d << 8) | ((4u + d) << 16) | ((4u + d) << 24));
+          A[fm][d] = (mk & lut[fm].y) | (~mk & v);
+        }
+      }
     };
     // 16-bit values of K16 step j: two per dword via the per-marker table
     auto decode = [&](const uint2* src2, int j, u32x4* A) {
@@ -1731,12 +1769,19 @@ __global__ __launch_bounds__(NW * 64) void gemm_wide_kernel(GemmArgs a) {
     u32x4 araw[WMF];  // FP8 form: the next chunk's code rows, read a step early
     constexpr bool SY = F8 && W2;  // shared selectors (spread / decode_y / decode8_y)
     uint32_t Y0[SY ? WMF : 1][4], Y1[SY ? WMF : 1][4];  // selectors of the first / second code dword
-    read_a(0, acur);
-    read_b(0, 0, bh[0], bl[0]);
+    uint2 dg8[WMF];  // 8-bit dosages: the two dwords of the step being decoded
+    if constexpr (G8) {
+      read_b(0, 0, bh[0], bl[0]);
+      read_g8(0, 0, dg8);
+      decode_g8(dg8, A[0]);
+    } else {
+      read_a(0, acur);
+      read_b(0, 0, bh[0], bl[0]);
+    }
     if constexpr (SY) {
       spread(acur, 0, Y0);
       decode_y(Y0, 0, A[0]);
-    } else {
+    } else if constexpr (!G8) {
       decode(acur, 0, A[0]);
     }
     if constexpr (F8 && !W2) decode8(acur, 0, A8[0]);
@@ -1771,24 +1816,31 @@ __global__ __launch_bounds__(NW * 64) void gemm_wide_kernel(GemmArgs a) {
         }
         if (j < 3) {
           read_b(st, j + 1, bh[ns], bl[ns]);
-          if constexpr (SY)
+          if constexpr (G8) {
+            read_g8(st, j + 1, dg8);
+            decode_g8(dg8, A[ns]);
+          } else if constexpr (SY) {
             decode_y(j + 1 < 2 ? Y0 : Y1, j + 1, A[ns]);
-          else
+          } else {
             decode(acur, j + 1, A[ns]);
+          }
         } else {
           // own copies of chunk ch+1 done (the NSTAGE-2 later chunks may
           // still be in flight) and own LDS reads of this chunk done; then
           // every wave's (a plain s_barrier: a workgroup fence here would
           // wait for every copy in flight)
           __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0((NSTAGE - 2) * CHUNK_OPS));
-          if constexpr (!F8) read_a(st1, anext);  // this wave's own copies: no barrier needed
+          if constexpr (!F8 && !G8) read_a(st1, anext);  // this wave's own copies: no barrier needed
           if constexpr (F8) pick_a(araw, anext);
           asm volatile("s_barrier" ::: "memory");
           // LDS reads before the copies: a read issued after a
           // direct-to-LDS load is held until that load completes
           read_b(st1, 0, bh[ns], bl[ns]);
+          if constexpr (G8) read_g8(st1, 0, dg8);  // own copies of chunk ch + 1 have landed
           if constexpr (!F8) dma(ch + NSTAGE, st);  // the FP8 form copies beside its lo MFMAs
-          if constexpr (SY) {
+          if constexpr (G8) {
+            decode_g8(dg8, A[ns]);
+          } else if constexpr (SY) {
             spread(anext, 0, Y0);
             decode_y(Y0, 0, A[ns]);
           } else {
@@ -2105,7 +2157,11 @@ TileShape tile_shape(int idx) { return kShapes[idx]; }
 int wgemm_tile() { return kWShape; }
 
 template <int PREC, int MODE>
-static const void* gemm_fn_g8(int idx) {  // 8-bit dosages: register-staged shapes only
+static const void* gemm_fn_g8(int idx) {  // 8-bit dosages: wide tiles 0 and 1 for the FP16 split
+  if constexpr (PREC == kSplit16) {
+    if (idx == 0) return (const void*)gemm_wide_kernel<PREC, MODE, 4, 4, 4, true>;
+    if (idx == 1) return (const void*)gemm_wide_kernel<PREC, MODE, 8, 2, 4, true>;
+  }
   if constexpr (g8_supported(PREC)) {
     switch (idx) {
       case 3: return (const void*)gemm_kernel<PREC, 4, 2, 4, MODE, true>;
@@ -2147,6 +2203,7 @@ static const void* gemm_fn(int idx) {
 
 static TileShape effective_shape(int idx, int prec, bool g8 = false) {
   const bool wide = idx <= 1 || idx == 6;
+  if (g8 && prec == kSplit16 && idx <= 1) return kShapes[idx];
   if (g8) return kShapes[wide ? 2 : idx];
   if (prec == kSplit8) return kShapes[(idx == 1 || idx == 6) ? idx : 0];
   if (wide && prec == kFP32) return kShapes[2];

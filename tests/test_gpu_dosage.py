@@ -37,8 +37,9 @@ def _debug_plan(tgw, n, V, precision, tile=-1):
 
 
 @pytest.mark.parametrize("precision", PRECS8)
-@pytest.mark.parametrize("n,m,p,tile", [(300, 70, 40, 0), (2000, 1100, 130, 2), (2000, 1100, 130, 3),
-                                        (1999, 700, 70, 4), (1999, 700, 70, 5)])
+@pytest.mark.parametrize("n,m,p,tile", [(300, 70, 40, 0), (2000, 1100, 130, 1), (2000, 1100, 130, 2),
+                                        (2000, 1100, 130, 3), (1999, 700, 70, 4), (1999, 700, 70, 5),
+                                        (1999, 1300, 300, 0)])
 def test_dosage8_contraction_exact_integers(tgw, precision, n, m, p, tile):
     """q - c with the integer c = round(mu) is exact in FP16 and FP32: the raw
     contraction equals int64 arithmetic bit for bit (no missing bytes)."""
@@ -151,18 +152,19 @@ def test_dosage8_unsupported_and_shape_errors(tgw):
     assert e.value.status == tgw.ERR_SHAPE
 
 
-@pytest.mark.parametrize("precision", PRECS8)
-def test_dosage8_full_width_against_oracle(tgw, precision):
+@pytest.mark.parametrize("precision,tile", [("split16", 0), ("split16", 1), ("split16", 2), ("fp32", -1)])
+def test_dosage8_full_width_against_oracle(tgw, precision, tile):
     """N = 23,000, P = 2,048: 1,536 markers (three 512-marker tiles) from the
-    device generator, every output against the oracle."""
+    device generator, every output against the oracle; the FP16 split on the
+    two wide tiles and a register-staged one."""
     spec = cohort_spec("cfg3")
     n = spec.n_samples
     m0, m1 = 40_000, 41_536
     rows = dosage8_rows_torch(spec, m0, m1, "cuda").cpu().numpy()
     np.testing.assert_array_equal(rows[:64], dosage8_rows_np(spec, np.arange(m0, m0 + 64)))
     C, Y = panel_inputs(spec, 0)
-    say(f"case: dosage8 N={n} P={Y.shape[1]} markers [{m0}, {m1}) {precision}")
-    res, _, _ = gpu_scan(C, [Y], rows, precision, code=tgw.CODE_DOSAGE8)
+    say(f"case: dosage8 N={n} P={Y.shape[1]} markers [{m0}, {m1}) {precision} tile {tile}")
+    res, _, _ = gpu_scan(C, [Y], rows, precision, code=tgw.CODE_DOSAGE8, plan_kw={"tile": tile})
     ref = oracle_scan(oracle.decode_dosage8(rows, n), C, Y)
-    err = compare(res[0], ref, ref["df"], f"dosage8 full width {precision} ")
-    say(f"[dosage8 full width {precision}] {err}")
+    err = compare(res[0], ref, ref["df"], f"dosage8 full width {precision} tile {tile} ")
+    say(f"[dosage8 full width {precision} tile {tile}] {err}")
