@@ -45,7 +45,11 @@ __host__ __device__ constexpr int block_bytes(int prec) { return prec == kSplit8
 // of its own: Q^T g runs on the FP16 split)
 __host__ __device__ constexpr int wprec(int prec) { return prec == kSplit8 ? kSplit16 : prec; }
 __host__ __device__ constexpr bool f16_scaled(int prec) { return prec == kSplit16 || prec == kSplit8; }
-enum Mode { kRaw = 0, kTest = 1 };
+// kRaw: raw FP32 products; kTest: the fused test epilogue; kRawHL: raw
+// products of a split operand whose hi parts sit in columns 0..15 and lo parts
+// in columns 16..31 of the hi half (one matrix-core pass), summed per slot
+enum Mode { kRaw = 0, kTest = 1, kRawHL = 2 };
+constexpr int kHLSlots = 16;  // covariate slots of the packed hi|lo operand
 
 // per-marker statistics of one marker block
 struct MarkerStat {
@@ -172,7 +176,7 @@ struct BindArgs {
 hipError_t launch_qr(const double* C, int64_t ldc, int64_t n, int64_t n_pad, int q, double* X, double* Q,
                      double* rdiag, int32_t* flags, hipStream_t s);
 hipError_t launch_cov_operands(const double* Q, int64_t n, int64_t n_pad, int q, void* const* wop,
-                               hipStream_t s);
+                               void* const* wop_hl, hipStream_t s);
 hipError_t launch_prep(const void* Y, int y_fp64, int64_t ldy, int64_t n, int64_t n_pad, int64_t P,
                        const double* Q, int q, int prec, void* yop, float* scale, float* invny, float* cw,
                        uint8_t* lscale, int32_t* flags, hipStream_t s);

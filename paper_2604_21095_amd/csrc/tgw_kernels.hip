@@ -327,7 +327,6 @@ __global__ __launch_bounds__(kQrThreads) void qr_kernel(const double* __restrict
                                                         int64_t n_pad, int q, double* __restrict__ X,
                                                         double* __restrict__ Q, double* rdiag,
                                                         int32_t* flags) {
-  __shared__ double sh[kQrThreads / 64];
   __shared__ double vtv_s[kMaxCov + 1];
   const int tid = threadIdx.x;
   // load [1 | C]; pad rows are zero
@@ -354,6 +353,26 @@ __global__ __launch_bounds__(kQrThreads) void qr_kernel(const double* __restrict
   __shared__ double shv[(kQrThreads / 64) * CB];
   __shared__ double dv_s[NQ];
   __shared__ double f_s[NQ];
+  // A thread takes its rows RPI at a time (i, i + kQrThreads, ...) and
+  // reads them for CB columns before it uses any of them, so that the loads
+  // of a pass are in flight together; a row past n is clamped to row i and a
+  // column past q - 1 to q - 1 (valid addresses whose values are not used).
+  // The order of the sums and updates per row is the plain one.
+  constexpr int RPI = 4;
+  struct Rows {
+    int64_t i[RPI];
+    bool ok[RPI];
+  };
+  auto rows_at = [&](int64_t i) {
+    Rows r;
+#pragma unroll
+    for (int u = 0; u < RPI; ++u) {
+      const int64_t ii = i + (int64_t)u * kQrThreads;
+      r.ok[u] = ii < n;
+      r.i[u] = r.ok[u] ? ii : i;
+    }
+    return r;
+  };
   // dv_s[k] = sum over rows i >= i0 of v[i] * W[k][i], for j0 <= k < q
   auto dots = [&](const double* v, const double* W, int j0, int64_t i0) {
     for (int k0 = j0; k0 < q; k0 += CB) {
@@ -361,11 +380,24 @@ __global__ __launch_bounds__(kQrThreads) void qr_kernel(const double* __restrict
 #pragma unroll
       for (int t = 0; t < CB; ++t) d[t] = 0.0;
 #pragma unroll 1
-      for (int64_t i = i0 + tid; i < n; i += kQrThreads) {
-        const double vi = v[i];
+      for (int64_t i = i0 + tid; i < n; i += RPI * kQrThreads) {
+        const Rows r = rows_at(i);
+        double vv[RPI], w[RPI][CB];
+#pragma unroll
+        for (int u = 0; u < RPI; ++u) vv[u] = v[r.i[u]];
+#pragma unroll
+        for (int t = 0; t < CB; ++t) {
+          const int64_t col = (int64_t)(k0 + t < q ? k0 + t : q - 1) * n_pad;
+#pragma unroll
+          for (int u = 0; u < RPI; ++u) w[u][t] = W[col + r.i[u]];
+        }
 #pragma unroll
         for (int t = 0; t < CB; ++t)
-          if (k0 + t < q) d[t] += vi * W[(int64_t)(k0 + t) * n_pad + i];
+#pragma unroll
+          for (int u = 0; u < RPI; ++u) {
+            const double e = d[t] + vv[u] * w[u][t];
+            d[t] = r.ok[u] ? e : d[t];
+          }
       }
       block_sum_vec<kQrThreads, CB>(d, shv);
       if (tid == 0) {
@@ -375,6 +407,34 @@ __global__ __launch_bounds__(kQrThreads) void qr_kernel(const double* __restrict
       }
     }
     __syncthreads();
+  };
+  // W[k][i] -= f_s[k] * v[i] for rows i >= i0 and k0 <= k < q
+  auto reflect = [&](const double* v, double* W, int k_begin, int64_t i0) {
+    for (int k0 = k_begin; k0 < q; k0 += CB) {
+#pragma unroll 1
+      for (int64_t i = i0 + tid; i < n; i += RPI * kQrThreads) {
+        const Rows r = rows_at(i);
+        double vv[RPI], w[RPI][CB];
+#pragma unroll
+        for (int u = 0; u < RPI; ++u) vv[u] = v[r.i[u]];
+#pragma unroll
+        for (int t = 0; t < CB; ++t) {
+          const int64_t col = (int64_t)(k0 + t < q ? k0 + t : q - 1) * n_pad;
+#pragma unroll
+          for (int u = 0; u < RPI; ++u) w[u][t] = W[col + r.i[u]];
+        }
+#pragma unroll
+        for (int t = 0; t < CB; ++t) {
+          if (k0 + t < q) {
+            const int64_t col = (int64_t)(k0 + t) * n_pad;
+            const double f = f_s[k0 + t];
+#pragma unroll
+            for (int u = 0; u < RPI; ++u)
+              if (r.ok[u]) W[col + r.i[u]] = w[u][t] - f * vv[u];
+          }
+        }
+      }
+    }
   };
   for (int j = 0; j < q; ++j) {
     double* xj = X + (int64_t)j * n_pad;
@@ -393,12 +453,7 @@ __global__ __launch_bounds__(kQrThreads) void qr_kernel(const double* __restrict
         f_s[k] = vtv > 0.0 ? 2.0 * (dv_s[k] + v0 * X[(int64_t)k * n_pad + j]) / vtv : 0.0;
     }
     __syncthreads();
-#pragma unroll 1
-    for (int64_t i = j + tid; i < n; i += kQrThreads) {
-      const double vi = xj[i];
-#pragma unroll 1
-      for (int k = j + 1; k < q; ++k) X[(int64_t)k * n_pad + i] -= f_s[k] * vi;
-    }
+    reflect(xj, X, j + 1, j);
     __syncthreads();
   }
   // Q = H_0 ... H_{q-1} [I_q; 0], the reflections applied from the last
@@ -413,12 +468,7 @@ __global__ __launch_bounds__(kQrThreads) void qr_kernel(const double* __restrict
       for (int k = j; k < q; ++k) f_s[k] = vtv > 0.0 ? 2.0 * dv_s[k] / vtv : 0.0;
     }
     __syncthreads();
-#pragma unroll 1
-    for (int64_t i = j + tid; i < n; i += kQrThreads) {
-      const double vi = xj[i];
-#pragma unroll 1
-      for (int k = j; k < q; ++k) Q[(int64_t)k * n_pad + i] -= f_s[k] * vi;
-    }
+    reflect(xj, Q, j, j);
     __syncthreads();
   }
   if (tid == 0) {
@@ -431,10 +481,25 @@ __global__ __launch_bounds__(kQrThreads) void qr_kernel(const double* __restrict
   }
 }
 
+// the hi and lo parts of a split operand value, as store_operand forms them
+__device__ inline void split_parts(int prec, double v, uint32_t* hb, uint32_t* lb) {
+  if (prec == kSplit16) {
+    const double vs = v * (double)kF16Scale;
+    *hb = f16_bits_rn((float)vs);
+    *lb = f16_bits_rn((float)(vs - (double)f16_to_float(*hb)));
+  } else {
+    *hb = bf16_bits_rne((float)v);
+    *lb = bf16_bits_rne((float)(v - (double)bf16_to_float(*hb)));
+  }
+}
+
 // operand blocks of the covariate columns used for Q^T g: slot k <- Q[:, k]
 // for 1 <= k < q, slot 0 and slots >= q are zero.  One 32-column block.
+// When q <= 16 the split forms also get a packed block (hl): the hi part of
+// slot k in column k and its lo part in column k + 16 of the hi half, the lo
+// half zero, so that one matrix-core pass forms both products.
 __global__ void cov_operand_kernel(const double* __restrict__ Q, int64_t n, int64_t n_pad, int q, void* wop_fp32,
-                                   void* wop_split, void* wop_split16) {
+                                   void* wop_split, void* wop_split16, void* hl_split, void* hl_split16) {
   const int n_chunks = (int)(n_pad / kChunk);
   const int64_t total = n_pad * kColBlock;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
@@ -446,6 +511,18 @@ __global__ void cov_operand_kernel(const double* __restrict__ Q, int64_t n, int6
     store_operand(wop_split, kSplit, k, i, n_chunks, v, &st);
     store_operand(wop_split16, kSplit16, k, i, n_chunks, v, &st);
     store_operand(wop_fp32, kFP32, k, i, n_chunks, v, &st);
+    if (k < kHLSlots && q <= kHLSlots) {
+#pragma unroll
+      for (int f = 0; f < 2; ++f) {
+        uint16_t* p = (uint16_t*)(f == 0 ? hl_split : hl_split16);
+        uint32_t hb, lb;
+        split_parts(f == 0 ? kSplit : kSplit16, v, &hb, &lb);
+        p[operand_index_split(k, i, n_chunks, 0)] = (uint16_t)hb;
+        p[operand_index_split(k + kHLSlots, i, n_chunks, 0)] = (uint16_t)lb;
+        p[operand_index_split(k, i, n_chunks, 1)] = 0;
+        p[operand_index_split(k + kHLSlots, i, n_chunks, 1)] = 0;
+      }
+    }
   }
 }
 
@@ -1176,6 +1253,8 @@ __device__ __forceinline__ void finish_block(const float* stage, const GemmArgs&
 template <int PREC, int NW, int WMF, int WN, int MODE, bool G8 = false>
 __global__ __launch_bounds__(NW * 64) void gemm_kernel(GemmArgs a) {
   static_assert(!G8 || g8_supported(PREC), "8-bit dosages run the FP32 and FP16 split forms");
+  static_assert(MODE != kRawHL || (PREC != kFP32 && WN == 1), "the packed hi|lo operand is one split block");
+  constexpr bool LO_PASS = MODE != kRawHL;
   constexpr int NT = NW * 64;
   constexpr int TM = NW * WMF * 32;
   constexpr int TILE_BYTES = WN * kBlockBytes;
@@ -1285,7 +1364,7 @@ __global__ __launch_bounds__(NW * 64) void gemm_kernel(GemmArgs a) {
 #pragma unroll
         for (int fn = 0; fn < WN; ++fn) {
           bh[fn] = *(const u32x4*)(tile + fn * kBlockBytes + (lane * 8) * 2);
-          bl[fn] = *(const u32x4*)(tile + fn * kBlockBytes + (2048 + lane * 8) * 2);
+          if constexpr (LO_PASS) bl[fn] = *(const u32x4*)(tile + fn * kBlockBytes + (2048 + lane * 8) * 2);
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -1322,22 +1401,25 @@ __global__ __launch_bounds__(NW * 64) void gemm_kernel(GemmArgs a) {
 #pragma unroll
             for (int fn = 0; fn < WN; ++fn) {
               nh[fn] = *(const u32x4*)(tile + fn * kBlockBytes + ((j + 1) * 512 + lane * 8) * 2);
-              nl[fn] = *(const u32x4*)(tile + fn * kBlockBytes + (2048 + (j + 1) * 512 + lane * 8) * 2);
+              if constexpr (LO_PASS)
+                nl[fn] = *(const u32x4*)(tile + fn * kBlockBytes + (2048 + (j + 1) * 512 + lane * 8) * 2);
             }
           }
 #pragma unroll
           for (int fn = 0; fn < WN; ++fn)
 #pragma unroll
             for (int fm = 0; fm < WMF; ++fm) acc[fm][fn] = mfma16<PREC>(A[fm], bh[fn], acc[fm][fn]);
+          if constexpr (LO_PASS) {
 #pragma unroll
-          for (int fn = 0; fn < WN; ++fn)
+            for (int fn = 0; fn < WN; ++fn)
 #pragma unroll
-            for (int fm = 0; fm < WMF; ++fm) acc[fm][fn] = mfma16<PREC>(A[fm], bl[fn], acc[fm][fn]);
+              for (int fm = 0; fm < WMF; ++fm) acc[fm][fn] = mfma16<PREC>(A[fm], bl[fn], acc[fm][fn]);
+          }
           if (j < 3) {
 #pragma unroll
             for (int fn = 0; fn < WN; ++fn) {
               bh[fn] = nh[fn];
-              bl[fn] = nl[fn];
+              if constexpr (LO_PASS) bl[fn] = nl[fn];
             }
           }
         }
@@ -1384,7 +1466,24 @@ __global__ __launch_bounds__(NW * 64) void gemm_kernel(GemmArgs a) {
     }
 
     // ---------------------------------------------------------------- epilogue
-    if constexpr (MODE == kRaw) {
+    if constexpr (MODE == kRawHL) {
+      // slot r32 < 16: the hi product (column r32) plus the lo product
+      // (column r32 + 16, held by lane r32 + 16 of this lane half); slots
+      // 16..31 are zero
+      if (ctile < a.n_cblocks) {
+        const ColBlock blk = a.cblocks[ctile];
+#pragma unroll
+        for (int fm = 0; fm < WMF; ++fm)
+#pragma unroll
+          for (int i = 0; i < 16; ++i) {
+            const float v = acc[fm][0][i];
+            const float o = __shfl_xor(v, kHLSlots);
+            const int64_t mr = rowbase + fm * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
+            if (mr < a.nm && r32 < blk.ncol)
+              gstore(a.raw_out + mr * a.raw_ld + blk.col0 + r32, r32 < kHLSlots ? v + o : 0.0f);
+          }
+      }
+    } else if constexpr (MODE == kRaw) {
 #pragma unroll
       for (int fn = 0; fn < WN; ++fn) {
         const int cb = ctile * WN + fn;
@@ -2213,6 +2312,14 @@ static TileShape effective_shape(int idx, int prec, bool g8 = false) {
 TileShape tile_shape_for(int idx, int prec, bool g8) { return effective_shape(idx, prec, g8); }
 
 static const void* gemm_fn_any(int idx, int prec, int mode, bool g8 = false) {
+  if (mode == kRawHL) {  // the Q^T g shape with the packed hi|lo covariate operand
+    if (idx != kWShape) return nullptr;
+    if (prec == kSplit16)
+      return g8 ? (const void*)gemm_kernel<kSplit16, 8, 2, 1, kRawHL, true>
+                : (const void*)gemm_kernel<kSplit16, 8, 2, 1, kRawHL>;
+    if (prec == kSplit && !g8) return (const void*)gemm_kernel<kSplit, 8, 2, 1, kRawHL>;
+    return nullptr;
+  }
   if (g8) {
     if (prec == kSplit16) return mode == kRaw ? gemm_fn_g8<kSplit16, kRaw>(idx) : gemm_fn_g8<kSplit16, kTest>(idx);
     if (prec == kFP32) return mode == kRaw ? gemm_fn_g8<kFP32, kRaw>(idx) : gemm_fn_g8<kFP32, kTest>(idx);
@@ -2258,9 +2365,10 @@ hipError_t launch_qr(const double* C, int64_t ldc, int64_t n, int64_t n_pad, int
 }
 
 hipError_t launch_cov_operands(const double* Q, int64_t n, int64_t n_pad, int q, void* const* wop,
-                               hipStream_t s) {
+                               void* const* wop_hl, hipStream_t s) {
+  if (q <= kHLSlots && (!wop_hl[kSplit] || !wop_hl[kSplit16])) return hipErrorInvalidValue;
   hipLaunchKernelGGL(cov_operand_kernel, dim3(256), dim3(256), 0, s, Q, n, n_pad, q, wop[kFP32], wop[kSplit],
-                     wop[kSplit16]);
+                     wop[kSplit16], wop_hl[kSplit], wop_hl[kSplit16]);
   return hipGetLastError();
 }
 

@@ -83,6 +83,7 @@ struct tgw_covariates {
   int q = 0, n_chunks = 0;
   double* Q = nullptr;       // [q][n_pad]
   void* wop[kNumPrec] = {};  // Q^T g operand block per precision (the FP8 form uses the FP16 split's)
+  void* wop_hl[kNumPrec] = {};  // packed hi|lo Q^T g blocks of the split forms (q <= 16 only)
 };
 
 struct tgw_panel {
@@ -120,6 +121,7 @@ struct tgw_plan {
   int tile = 0;
   std::vector<int> grid_main;  // per tile shape
   int grid_w = 0;
+  int w_mode = kRaw;  // kRawHL when every panel's q fits the packed hi|lo operand
   // 8-bit dosage rows (the FP32 and FP16 split forms): own tile choice and grids
   int tile8 = 2;
   std::vector<int> grid_main8;
@@ -175,7 +177,10 @@ extern "C" tgw_status tgw_tile_shape(int32_t idx, int32_t* tile_markers, int32_t
 extern "C" void tgw_covariates_free(tgw_covariates* cov) {
   if (!cov) return;
   (void)hipFree(cov->Q);
-  for (int k = 0; k < kNumPrec; ++k) (void)hipFree(cov->wop[k]);
+  for (int k = 0; k < kNumPrec; ++k) {
+    (void)hipFree(cov->wop[k]);
+    (void)hipFree(cov->wop_hl[k]);
+  }
   delete cov;
 }
 
@@ -211,10 +216,13 @@ extern "C" tgw_status tgw_fit_covariates(int64_t n_samples, int32_t n_cov, const
   if (e == hipSuccess) e = dmalloc(&flags, 2);
   for (int k = 0; k < kNumPrec; ++k)
     if (e == hipSuccess && wprec(k) == k) e = hipMalloc(&cov->wop[k], (size_t)cov->n_chunks * kBlockBytes);
+  if (cov->q <= kHLSlots)
+    for (int k : {(int)kSplit, (int)kSplit16})
+      if (e == hipSuccess) e = hipMalloc(&cov->wop_hl[k], (size_t)cov->n_chunks * kBlockBytes);
   if (e == hipSuccess) e = hipMemsetAsync(flags, 0, 2 * sizeof(int32_t), s);
   if (e == hipSuccess) e = launch_qr(d_C, ldc, n_samples, cov->n_pad, cov->q, X, cov->Q, rdiag, flags, s);
   if (e == hipSuccess)
-    e = launch_cov_operands(cov->Q, n_samples, cov->n_pad, cov->q, cov->wop, s);
+    e = launch_cov_operands(cov->Q, n_samples, cov->n_pad, cov->q, cov->wop, cov->wop_hl, s);
   int32_t hf[2] = {0, 0};
   if (e == hipSuccess) e = hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -455,6 +463,9 @@ extern "C" tgw_status tgw_plan_create(const tgw_panel* const* panels, int32_t n_
 
   std::vector<ColBlock> cbm, cbw;
   std::vector<PanelDev> pdv;
+  bool hl = wprec(pl->prec) != kFP32;
+  for (int j = 0; j < n_panels; ++j) hl = hl && panels[j]->cov->wop_hl[wprec(pl->prec)] != nullptr;
+  pl->w_mode = hl ? kRawHL : kRaw;
   for (int j = 0; j < n_panels; ++j) {
     const tgw_panel* p = panels[j];
     const int64_t nb = p->P_pad / kColBlock;
@@ -467,7 +478,7 @@ extern "C" tgw_status tgw_plan_create(const tgw_panel* const* panels, int32_t n_
       cbm.push_back(c);
     }
     ColBlock w{};
-    w.op = (const char*)p->cov->wop[wprec(pl->prec)];
+    w.op = (const char*)(hl ? p->cov->wop_hl[wprec(pl->prec)] : p->cov->wop[wprec(pl->prec)]);
     w.panel = j;
     w.col0 = j * kSlots;
     w.ncol = kSlots;
@@ -513,10 +524,10 @@ extern "C" tgw_status tgw_plan_create(const tgw_panel* const* panels, int32_t n_
     return hip_fail(e, "tgw_plan_create");
   }
   for (int i = 0; i < n_tile_shapes(); ++i) pl->grid_main.push_back(gemm_grid(i, pl->prec, kTest, pl->n_cu));
-  pl->grid_w = gemm_grid(wgemm_tile(), wprec(pl->prec), kRaw, pl->n_cu);
+  pl->grid_w = gemm_grid(wgemm_tile(), wprec(pl->prec), pl->w_mode, pl->n_cu);
   if (g8_supported(pl->prec)) {
     for (int i = 0; i < n_tile_shapes(); ++i) pl->grid_main8.push_back(gemm_grid(i, pl->prec, kTest, pl->n_cu, true));
-    pl->grid_w8 = gemm_grid(wgemm_tile(), wprec(pl->prec), kRaw, pl->n_cu, true);
+    pl->grid_w8 = gemm_grid(wgemm_tile(), wprec(pl->prec), pl->w_mode, pl->n_cu, true);
     if (o.tile < 0) {
       auto cache8 = tune_cache_read();
       auto it8 = cache8.find(tune_key(pl) + "/g8");
@@ -624,7 +635,7 @@ static hipError_t enqueue_block_stats(tgw_plan* pl, const ScanCall& c, int64_t m
   a.raw_out = pl->wws;
   a.raw_ld = (int64_t)pl->n_panels * kSlots;
   const bool g8 = c.code == TGW_CODE_DOSAGE8;
-  e = launch_gemm(wgemm_tile(), wprec(pl->prec), kRaw, a, g8 ? pl->grid_w8 : pl->grid_w, s, g8);
+  e = launch_gemm(wgemm_tile(), wprec(pl->prec), pl->w_mode, a, g8 ? pl->grid_w8 : pl->grid_w, s, g8);
   if (e != hipSuccess) return e;
   return launch_finalize(pl->mstat, pl->wws, pl->invh, nm, pl->n_panels,
                          f16_scaled(pl->prec) ? 1.0f / kF16Scale : 1.0f, s);
