@@ -48,8 +48,11 @@ __host__ __device__ constexpr bool f16_scaled(int prec) { return prec == kSplit1
 // kRaw: raw FP32 products; kTest: the fused test epilogue; kRawHL: raw
 // products of a split operand whose hi parts sit in columns 0..15 and lo parts
 // in columns 16..31 of the hi half (one matrix-core pass), summed per slot
+// (the Q^T g contraction of the split forms)
 enum Mode { kRaw = 0, kTest = 1, kRawHL = 2 };
-constexpr int kHLSlots = 16;  // covariate slots of the packed hi|lo operand
+constexpr int kHLSlots = 16;  // covariate slots per packed hi|lo operand block
+// packed hi|lo blocks of a covariate basis with q columns
+__host__ __device__ constexpr int hl_blocks(int q) { return q <= kHLSlots ? 1 : 2; }
 
 // per-marker statistics of one marker block
 struct MarkerStat {

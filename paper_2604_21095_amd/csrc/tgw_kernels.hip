@@ -495,8 +495,9 @@ __device__ inline void split_parts(int prec, double v, uint32_t* hb, uint32_t* l
 
 // operand blocks of the covariate columns used for Q^T g: slot k <- Q[:, k]
 // for 1 <= k < q, slot 0 and slots >= q are zero.  One 32-column block.
-// When q <= 16 the split forms also get a packed block (hl): the hi part of
-// slot k in column k and its lo part in column k + 16 of the hi half, the lo
+// The split forms take packed blocks (hl) instead, one per 16 slots (one
+// block when q <= 16, else two): slot k goes to block k / 16, its hi part in
+// column k % 16 and its lo part in column k % 16 + 16 of the hi half, the lo
 // half zero, so that one matrix-core pass forms both products.
 __global__ void cov_operand_kernel(const double* __restrict__ Q, int64_t n, int64_t n_pad, int q, void* wop_fp32,
                                    void* wop_split, void* wop_split16, void* hl_split, void* hl_split16) {
@@ -511,16 +512,17 @@ __global__ void cov_operand_kernel(const double* __restrict__ Q, int64_t n, int6
     store_operand(wop_split, kSplit, k, i, n_chunks, v, &st);
     store_operand(wop_split16, kSplit16, k, i, n_chunks, v, &st);
     store_operand(wop_fp32, kFP32, k, i, n_chunks, v, &st);
-    if (k < kHLSlots && q <= kHLSlots) {
+    if (k < hl_blocks(q) * kHLSlots) {
+      const int64_t ch = 32 * (k / kHLSlots) + k % kHLSlots;  // hi column; lo column ch + 16
 #pragma unroll
       for (int f = 0; f < 2; ++f) {
         uint16_t* p = (uint16_t*)(f == 0 ? hl_split : hl_split16);
         uint32_t hb, lb;
         split_parts(f == 0 ? kSplit : kSplit16, v, &hb, &lb);
-        p[operand_index_split(k, i, n_chunks, 0)] = (uint16_t)hb;
-        p[operand_index_split(k + kHLSlots, i, n_chunks, 0)] = (uint16_t)lb;
-        p[operand_index_split(k, i, n_chunks, 1)] = 0;
-        p[operand_index_split(k + kHLSlots, i, n_chunks, 1)] = 0;
+        p[operand_index_split(ch, i, n_chunks, 0)] = (uint16_t)hb;
+        p[operand_index_split(ch + kHLSlots, i, n_chunks, 0)] = (uint16_t)lb;
+        p[operand_index_split(ch, i, n_chunks, 1)] = 0;
+        p[operand_index_split(ch + kHLSlots, i, n_chunks, 1)] = 0;
       }
     }
   }
@@ -1467,9 +1469,10 @@ __global__ __launch_bounds__(NW * 64) void gemm_kernel(GemmArgs a) {
 
     // ---------------------------------------------------------------- epilogue
     if constexpr (MODE == kRawHL) {
-      // slot r32 < 16: the hi product (column r32) plus the lo product
-      // (column r32 + 16, held by lane r32 + 16 of this lane half); slots
-      // 16..31 are zero
+      // slot col0 + r32, r32 < 16: the hi product (column r32) plus the lo
+      // product (column r32 + 16, held by lane r32 + 16 of this lane half);
+      // a block of 32 columns (ncol = 32: the panel's only block) also
+      // writes zeros to the 16 slots after its own
       if (ctile < a.n_cblocks) {
         const ColBlock blk = a.cblocks[ctile];
 #pragma unroll
@@ -2366,7 +2369,7 @@ hipError_t launch_qr(const double* C, int64_t ldc, int64_t n, int64_t n_pad, int
 
 hipError_t launch_cov_operands(const double* Q, int64_t n, int64_t n_pad, int q, void* const* wop,
                                void* const* wop_hl, hipStream_t s) {
-  if (q <= kHLSlots && (!wop_hl[kSplit] || !wop_hl[kSplit16])) return hipErrorInvalidValue;
+  if (!wop_hl[kSplit] || !wop_hl[kSplit16]) return hipErrorInvalidValue;
   hipLaunchKernelGGL(cov_operand_kernel, dim3(256), dim3(256), 0, s, Q, n, n_pad, q, wop[kFP32], wop[kSplit],
                      wop[kSplit16], wop_hl[kSplit], wop_hl[kSplit16]);
   return hipGetLastError();

@@ -83,7 +83,7 @@ struct tgw_covariates {
   int q = 0, n_chunks = 0;
   double* Q = nullptr;       // [q][n_pad]
   void* wop[kNumPrec] = {};  // Q^T g operand block per precision (the FP8 form uses the FP16 split's)
-  void* wop_hl[kNumPrec] = {};  // packed hi|lo Q^T g blocks of the split forms (q <= 16 only)
+  void* wop_hl[kNumPrec] = {};  // packed hi|lo Q^T g blocks of the split forms (hl_blocks(q) of them)
 };
 
 struct tgw_panel {
@@ -121,7 +121,8 @@ struct tgw_plan {
   int tile = 0;
   std::vector<int> grid_main;  // per tile shape
   int grid_w = 0;
-  int w_mode = kRaw;  // kRawHL when every panel's q fits the packed hi|lo operand
+  int w_mode = kRaw;  // kRawHL for the split forms (packed hi|lo covariate operand)
+  int n_cb_w = 0;     // column blocks of the Q^T g contraction
   // 8-bit dosage rows (the FP32 and FP16 split forms): own tile choice and grids
   int tile8 = 2;
   std::vector<int> grid_main8;
@@ -216,9 +217,8 @@ extern "C" tgw_status tgw_fit_covariates(int64_t n_samples, int32_t n_cov, const
   if (e == hipSuccess) e = dmalloc(&flags, 2);
   for (int k = 0; k < kNumPrec; ++k)
     if (e == hipSuccess && wprec(k) == k) e = hipMalloc(&cov->wop[k], (size_t)cov->n_chunks * kBlockBytes);
-  if (cov->q <= kHLSlots)
-    for (int k : {(int)kSplit, (int)kSplit16})
-      if (e == hipSuccess) e = hipMalloc(&cov->wop_hl[k], (size_t)cov->n_chunks * kBlockBytes);
+  for (int k : {(int)kSplit, (int)kSplit16})
+    if (e == hipSuccess) e = hipMalloc(&cov->wop_hl[k], (size_t)hl_blocks(cov->q) * cov->n_chunks * kBlockBytes);
   if (e == hipSuccess) e = hipMemsetAsync(flags, 0, 2 * sizeof(int32_t), s);
   if (e == hipSuccess) e = launch_qr(d_C, ldc, n_samples, cov->n_pad, cov->q, X, cov->Q, rdiag, flags, s);
   if (e == hipSuccess)
@@ -463,8 +463,7 @@ extern "C" tgw_status tgw_plan_create(const tgw_panel* const* panels, int32_t n_
 
   std::vector<ColBlock> cbm, cbw;
   std::vector<PanelDev> pdv;
-  bool hl = wprec(pl->prec) != kFP32;
-  for (int j = 0; j < n_panels; ++j) hl = hl && panels[j]->cov->wop_hl[wprec(pl->prec)] != nullptr;
+  const bool hl = wprec(pl->prec) != kFP32;
   pl->w_mode = hl ? kRawHL : kRaw;
   for (int j = 0; j < n_panels; ++j) {
     const tgw_panel* p = panels[j];
@@ -477,12 +476,24 @@ extern "C" tgw_status tgw_plan_create(const tgw_panel* const* panels, int32_t n_
       c.ncol = (int32_t)std::min<int64_t>(kColBlock, p->P - b * kColBlock);
       cbm.push_back(c);
     }
-    ColBlock w{};
-    w.op = (const char*)(hl ? p->cov->wop_hl[wprec(pl->prec)] : p->cov->wop[wprec(pl->prec)]);
-    w.panel = j;
-    w.col0 = j * kSlots;
-    w.ncol = kSlots;
-    cbw.push_back(w);
+    if (hl) {  // slots 16 b .. 16 b + 15 from packed block b
+      const int nb = hl_blocks(p->cov->q);
+      for (int b = 0; b < nb; ++b) {
+        ColBlock w{};
+        w.op = (const char*)p->cov->wop_hl[wprec(pl->prec)] + (size_t)b * pl->n_chunks * kBlockBytes;
+        w.panel = j;
+        w.col0 = j * kSlots + b * kHLSlots;
+        w.ncol = nb == 1 ? kSlots : kHLSlots;
+        cbw.push_back(w);
+      }
+    } else {
+      ColBlock w{};
+      w.op = (const char*)p->cov->wop[wprec(pl->prec)];
+      w.panel = j;
+      w.col0 = j * kSlots;
+      w.ncol = kSlots;
+      cbw.push_back(w);
+    }
     PanelDev d{};
     d.scale = p->scale;
     d.invny = p->invny;
@@ -497,6 +508,7 @@ extern "C" tgw_status tgw_plan_create(const tgw_panel* const* panels, int32_t n_
     pdv.push_back(d);
   }
   pl->n_cb = (int)cbm.size();
+  pl->n_cb_w = (int)cbw.size();
   const int64_t per_marker = (int64_t)sizeof(uint4) + sizeof(MarkerStat) + (int64_t)n_panels * (kSlots + 1) * 4;
   int64_t MB = o.block_markers;
   if (MB == 0) MB = std::max<int64_t>(4096, std::min<int64_t>(1 << 20, (2ll << 30) / per_marker));
@@ -629,8 +641,8 @@ static hipError_t enqueue_block_stats(tgw_plan* pl, const ScanCall& c, int64_t m
   GemmArgs a = base_args(pl, c, m0, nm);
   const TileShape ws = tile_shape(wgemm_tile());
   a.cblocks = pl->d_cb_w;
-  a.n_cblocks = pl->n_panels;
-  a.n_ctiles = (int)((pl->n_panels + ws.wn_frags - 1) / ws.wn_frags);
+  a.n_cblocks = pl->n_cb_w;
+  a.n_ctiles = (int)((pl->n_cb_w + ws.wn_frags - 1) / ws.wn_frags);
   a.n_mtiles = (int)((nm + ws.tm() - 1) / ws.tm());
   a.raw_out = pl->wws;
   a.raw_ld = (int64_t)pl->n_panels * kSlots;

@@ -327,13 +327,15 @@ def test_determinism_resume_graph(tgw, precision, cut):
 
 
 def test_batching_equals_single(tgw):
-    """Several uneven panels in one plan give the same bits as one plan each."""
+    """Several uneven panels in one plan give the same bits as one plan each.
+    The K=20 panel (q = 21) takes two packed covariate blocks in the Q^T g
+    contraction, the others one."""
     spec = cohort_spec("cfg1")
     say("case: batching vs single panels")
     rng = np.random.default_rng(77)
     codes, packed, _, _ = cohort_arrays(spec, np.arange(2500))
     n = spec.n_samples
-    sizes = [(20, 2), (70, 5), (5, 0), (33, 9)]
+    sizes = [(20, 2), (70, 5), (5, 0), (33, 9), (12, 20)]
     Cs, Ys = [], []
     for p, k in sizes:
         Cs.append(rng.standard_normal((n, k)))
