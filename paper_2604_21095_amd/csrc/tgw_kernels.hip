@@ -1313,11 +1313,15 @@ __global__ __launch_bounds__(NW * 64) void gemm_kernel(GemmArgs a) {
         for (int i = 0; i < 16; ++i) acc[fm][fn][i] = 0.0f;
 
     u32x4 breg[WN][RPB];
-    // this lane's genotype bytes of the chunk: 8 (2-bit codes) or 32 (dosages)
+    // this lane's genotype bytes of the chunk: 8 (2-bit codes) or 32 (dosages).
+    // The 32-column shape (the Q^T g contraction) does little work per
+    // chunk, so it keeps a ring of AD chunks of its rows in flight to cover
+    // the memory latency (the chunk loop is unrolled by AD so that the ring
+    // is indexed statically); the others keep one chunk ahead.
+    constexpr int AD = WN == 1 ? (G8 ? 2 : 4) : 1;
     struct ARow {
       u32x4 q[G8 ? 2 : 1];
     };
-    ARow areg[WMF], anext[WMF];
     auto load_b = [&](int ch) {
 #pragma unroll
       for (int fn = 0; fn < WN; ++fn)
@@ -1347,19 +1351,8 @@ __global__ __launch_bounds__(NW * 64) void gemm_kernel(GemmArgs a) {
     // dword k (4 samples) of this lane's dosage bytes
     auto dword8 = [&](const ARow& r, int k) -> uint32_t { return k < 4 ? r.q[0][k] : r.q[G8 ? 1 : 0][k & 3]; };
 
-    load_b(0);
-    load_a(0, areg);
-    store_b(0);
-    __syncthreads();
-
-    const int nch = a.n_chunks;
-    for (int ch = 0; ch < nch; ++ch) {
-      const int cur = ch & 1;
-      const bool more = ch + 1 < nch;
-      if (more) {
-        load_b(ch + 1);
-        load_a(ch + 1, anext);
-      }
+    // one chunk's decode and matrix-core steps on the staged operand tile cur
+    auto compute = [&](const int cur, const ARow* areg) __attribute__((always_inline)) {
       const char* tile = smem + cur * TILE_BYTES;
       if constexpr (PREC != kFP32) {
         u32x4 bh[WN], bl[WN];
@@ -1461,10 +1454,53 @@ __global__ __launch_bounds__(NW * 64) void gemm_kernel(GemmArgs a) {
           }
         }
       }
-      if (more) store_b(cur ^ 1);
+    };
+
+    const int nch = a.n_chunks;
+    if constexpr (AD == 1) {
+      ARow areg[WMF], anext[WMF];
+      load_b(0);
+      load_a(0, areg);
+      store_b(0);
       __syncthreads();
+      for (int ch = 0; ch < nch; ++ch) {
+        const int cur = ch & 1;
+        const bool more = ch + 1 < nch;
+        if (more) {
+          load_b(ch + 1);
+          load_a(ch + 1, anext);
+        }
+        compute(cur, areg);
+        if (more) store_b(cur ^ 1);
+        __syncthreads();
 #pragma unroll
-      for (int fm = 0; fm < WMF; ++fm) areg[fm] = anext[fm];
+        for (int fm = 0; fm < WMF; ++fm) areg[fm] = anext[fm];
+      }
+    } else {
+      // ring[u] holds chunk ch0 + u (ch0 a multiple of AD, so that chunk
+      // sits in LDS buffer u & 1); once used it is refilled with chunk
+      // ch0 + u + AD (the last chunk again past the end: a valid row address
+      // whose bytes are not used)
+      ARow ring[AD][WMF];
+      load_b(0);
+#pragma unroll
+      for (int u = 0; u < AD; ++u) load_a(u < nch ? u : nch - 1, ring[u]);
+      store_b(0);
+      __syncthreads();
+      for (int ch0 = 0; ch0 < nch; ch0 += AD) {
+#pragma unroll
+        for (int u = 0; u < AD; ++u) {
+          const int ch = ch0 + u;
+          if (ch < nch) {
+            const bool more = ch + 1 < nch;
+            if (more) load_b(ch + 1);
+            compute(u & 1, ring[u]);
+            load_a(ch + AD < nch ? ch + AD : nch - 1, ring[u]);
+            if (more) store_b((u & 1) ^ 1);
+            __syncthreads();
+          }
+        }
+      }
     }
 
     // ---------------------------------------------------------------- epilogue
