@@ -2414,17 +2414,18 @@ hipError_t launch_cov_operands(const double* Q, int64_t n, int64_t n_pad, int q,
 hipError_t launch_prep(const void* Y, int y_fp64, int64_t ldy, int64_t n, int64_t n_pad, int64_t P,
                        const double* Q, int q, int prec, void* yop, float* scale, float* invny, float* cw,
                        uint8_t* lscale, int32_t* flags, hipStream_t s) {
-  // q <= QS slots; as many columns per workgroup as registers allow
+  // q <= QS slots; two columns per workgroup (at P = 2,048 and q = 11 this
+  // beats four, which leaves two waves per SIMD, and one), one for q > 24
   auto go = [&](auto kern, int cpw) {
     hipLaunchKernelGGL(kern, dim3((unsigned)((P + cpw - 1) / cpw)), dim3(kPrepThreads), 0, s, Y, y_fp64, ldy, n,
                        n_pad, P, Q, q, prec, yop, scale, invny, cw, lscale, flags);
   };
   if (q <= 4)
-    go(prep_kernel<4, 4>, 4);
+    go(prep_kernel<4, 2>, 2);
   else if (q <= 8)
-    go(prep_kernel<8, 4>, 4);
+    go(prep_kernel<8, 2>, 2);
   else if (q <= 12)
-    go(prep_kernel<12, 4>, 4);
+    go(prep_kernel<12, 2>, 2);
   else if (q <= 16)
     go(prep_kernel<16, 2>, 2);
   else if (q <= 24)
