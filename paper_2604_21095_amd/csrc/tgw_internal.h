@@ -178,7 +178,7 @@ struct BindArgs {
 // ---- launchers (kernels.hip) -------------------------------------------------
 hipError_t launch_qr(const double* C, int64_t ldc, int64_t n, int64_t n_pad, int q, double* X, double* Q,
                      double* rdiag, int32_t* flags, hipStream_t s);
-hipError_t launch_cov_operands(const double* Q, int64_t n, int64_t n_pad, int q, void* const* wop,
+hipError_t launch_cov_operands(const double* Q, int64_t n, int64_t n_pad, int q, void* wop_fp32,
                                void* const* wop_hl, hipStream_t s);
 hipError_t launch_prep(const void* Y, int y_fp64, int64_t ldy, int64_t n, int64_t n_pad, int64_t P,
                        const double* Q, int q, int prec, void* yop, float* scale, float* invny, float* cw,

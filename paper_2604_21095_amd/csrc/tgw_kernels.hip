@@ -183,6 +183,19 @@ __device__ inline int lo_shift(double maxlo) {
 }
 
 // lsh: the column's FP8 lo shift (FP16 hi + FP8 lo form only)
+// the hi and lo parts of a value in the BF16 split, or of 2^12 times it in
+// the FP16 split (round to nearest even, then the rounded remainder)
+__device__ inline void split_parts(int prec, double v, uint32_t* hb, uint32_t* lb) {
+  if (prec == kSplit16) {
+    const double vs = v * (double)kF16Scale;
+    *hb = f16_bits_rn((float)vs);
+    *lb = f16_bits_rn((float)(vs - (double)f16_to_float(*hb)));
+  } else {
+    *hb = bf16_bits_rne((float)v);
+    *lb = bf16_bits_rne((float)(v - (double)bf16_to_float(*hb)));
+  }
+}
+
 __device__ inline void store_operand(void* op, int prec, int64_t col, int64_t i, int n_chunks, double v,
                                      double* stored, int lsh = 0) {
   if (prec == kSplit8) {
@@ -193,26 +206,14 @@ __device__ inline void store_operand(void* op, int prec, int64_t col, int64_t i,
     ((uint16_t*)op)[operand_index_split(col, i, n_chunks, 0, kBlockBytes8 / 2)] = (uint16_t)hb;
     ((uint8_t*)op)[operand_index_lo8(col, i, n_chunks)] = (uint8_t)qb;
     *stored = hi + ldexp(e4m3_value(qb), -lsh);
-  } else if (prec == kSplit16) {
-    const double vs = v * (double)kF16Scale;
-    const uint32_t hb = f16_bits_rn((float)vs);
-    const double hi = (double)f16_to_float(hb);
-    const uint32_t lb = f16_bits_rn((float)(vs - hi));
-    const double lo = (double)f16_to_float(lb);
+  } else if (prec == kSplit16 || prec == kSplit) {
+    uint32_t hb, lb;
+    split_parts(prec, v, &hb, &lb);
     uint16_t* p = (uint16_t*)op;
     p[operand_index_split(col, i, n_chunks, 0)] = (uint16_t)hb;
     p[operand_index_split(col, i, n_chunks, 1)] = (uint16_t)lb;
-    *stored = hi + lo;
-  } else if (prec == kSplit) {
-    const float f = (float)v;
-    const uint32_t hb = bf16_bits_rne(f);
-    const double hi = (double)bf16_to_float(hb);
-    const uint32_t lb = bf16_bits_rne((float)(v - hi));
-    const double lo = (double)bf16_to_float(lb);
-    uint16_t* p = (uint16_t*)op;
-    p[operand_index_split(col, i, n_chunks, 0)] = (uint16_t)hb;
-    p[operand_index_split(col, i, n_chunks, 1)] = (uint16_t)lb;
-    *stored = hi + lo;
+    *stored = prec == kSplit16 ? (double)f16_to_float(hb) + (double)f16_to_float(lb)
+                               : (double)bf16_to_float(hb) + (double)bf16_to_float(lb);
   } else {
     const float f = (float)v;
     ((float*)op)[operand_index_fp32(col, i, n_chunks)] = f;
@@ -481,26 +482,15 @@ __global__ __launch_bounds__(kQrThreads) void qr_kernel(const double* __restrict
   }
 }
 
-// the hi and lo parts of a split operand value, as store_operand forms them
-__device__ inline void split_parts(int prec, double v, uint32_t* hb, uint32_t* lb) {
-  if (prec == kSplit16) {
-    const double vs = v * (double)kF16Scale;
-    *hb = f16_bits_rn((float)vs);
-    *lb = f16_bits_rn((float)(vs - (double)f16_to_float(*hb)));
-  } else {
-    *hb = bf16_bits_rne((float)v);
-    *lb = bf16_bits_rne((float)(v - (double)bf16_to_float(*hb)));
-  }
-}
 
 // operand blocks of the covariate columns used for Q^T g: slot k <- Q[:, k]
-// for 1 <= k < q, slot 0 and slots >= q are zero.  One 32-column block.
-// The split forms take packed blocks (hl) instead, one per 16 slots (one
+// for 1 <= k < q, slot 0 and slots >= q are zero.  FP32: one 32-column
+// block.  The split forms take packed blocks (hl), one per 16 slots (one
 // block when q <= 16, else two): slot k goes to block k / 16, its hi part in
 // column k % 16 and its lo part in column k % 16 + 16 of the hi half, the lo
 // half zero, so that one matrix-core pass forms both products.
 __global__ void cov_operand_kernel(const double* __restrict__ Q, int64_t n, int64_t n_pad, int q, void* wop_fp32,
-                                   void* wop_split, void* wop_split16, void* hl_split, void* hl_split16) {
+                                   void* hl_split, void* hl_split16) {
   const int n_chunks = (int)(n_pad / kChunk);
   const int64_t total = n_pad * kColBlock;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
@@ -509,8 +499,6 @@ __global__ void cov_operand_kernel(const double* __restrict__ Q, int64_t n, int6
     const int k = (int)(idx % kColBlock);
     const double v = (k >= 1 && k < q && i < n) ? Q[(int64_t)k * n_pad + i] : 0.0;
     double st;
-    store_operand(wop_split, kSplit, k, i, n_chunks, v, &st);
-    store_operand(wop_split16, kSplit16, k, i, n_chunks, v, &st);
     store_operand(wop_fp32, kFP32, k, i, n_chunks, v, &st);
     if (k < hl_blocks(q) * kHLSlots) {
       const int64_t ch = 32 * (k / kHLSlots) + k % kHLSlots;  // hi column; lo column ch + 16
@@ -2403,11 +2391,11 @@ hipError_t launch_qr(const double* C, int64_t ldc, int64_t n, int64_t n_pad, int
   return hipGetLastError();
 }
 
-hipError_t launch_cov_operands(const double* Q, int64_t n, int64_t n_pad, int q, void* const* wop,
+hipError_t launch_cov_operands(const double* Q, int64_t n, int64_t n_pad, int q, void* wop_fp32,
                                void* const* wop_hl, hipStream_t s) {
-  if (!wop_hl[kSplit] || !wop_hl[kSplit16]) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(cov_operand_kernel, dim3(256), dim3(256), 0, s, Q, n, n_pad, q, wop[kFP32], wop[kSplit],
-                     wop[kSplit16], wop_hl[kSplit], wop_hl[kSplit16]);
+  if (!wop_fp32 || !wop_hl[kSplit] || !wop_hl[kSplit16]) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(cov_operand_kernel, dim3(256), dim3(256), 0, s, Q, n, n_pad, q, wop_fp32, wop_hl[kSplit],
+                     wop_hl[kSplit16]);
   return hipGetLastError();
 }
 

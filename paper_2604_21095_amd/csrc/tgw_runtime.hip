@@ -82,8 +82,9 @@ struct tgw_covariates {
   int64_t n = 0, n_pad = 0;
   int q = 0, n_chunks = 0;
   double* Q = nullptr;       // [q][n_pad]
-  void* wop[kNumPrec] = {};  // Q^T g operand block per precision (the FP8 form uses the FP16 split's)
-  void* wop_hl[kNumPrec] = {};  // packed hi|lo Q^T g blocks of the split forms (hl_blocks(q) of them)
+  void* wop_fp32 = nullptr;     // Q^T g operand block of the FP32 form
+  void* wop_hl[kNumPrec] = {};  // packed hi|lo Q^T g blocks of the split forms (hl_blocks(q) of them; the
+                                // FP8 form uses the FP16 split's)
 };
 
 struct tgw_panel {
@@ -178,10 +179,8 @@ extern "C" tgw_status tgw_tile_shape(int32_t idx, int32_t* tile_markers, int32_t
 extern "C" void tgw_covariates_free(tgw_covariates* cov) {
   if (!cov) return;
   (void)hipFree(cov->Q);
-  for (int k = 0; k < kNumPrec; ++k) {
-    (void)hipFree(cov->wop[k]);
-    (void)hipFree(cov->wop_hl[k]);
-  }
+  (void)hipFree(cov->wop_fp32);
+  for (int k = 0; k < kNumPrec; ++k) (void)hipFree(cov->wop_hl[k]);
   delete cov;
 }
 
@@ -215,14 +214,13 @@ extern "C" tgw_status tgw_fit_covariates(int64_t n_samples, int32_t n_cov, const
   if (e == hipSuccess) e = dmalloc(&X, (size_t)cov->q * cov->n_pad);
   if (e == hipSuccess) e = dmalloc(&rdiag, (size_t)cov->q);
   if (e == hipSuccess) e = dmalloc(&flags, 2);
-  for (int k = 0; k < kNumPrec; ++k)
-    if (e == hipSuccess && wprec(k) == k) e = hipMalloc(&cov->wop[k], (size_t)cov->n_chunks * kBlockBytes);
+  if (e == hipSuccess) e = hipMalloc(&cov->wop_fp32, (size_t)cov->n_chunks * kBlockBytes);
   for (int k : {(int)kSplit, (int)kSplit16})
     if (e == hipSuccess) e = hipMalloc(&cov->wop_hl[k], (size_t)hl_blocks(cov->q) * cov->n_chunks * kBlockBytes);
   if (e == hipSuccess) e = hipMemsetAsync(flags, 0, 2 * sizeof(int32_t), s);
   if (e == hipSuccess) e = launch_qr(d_C, ldc, n_samples, cov->n_pad, cov->q, X, cov->Q, rdiag, flags, s);
   if (e == hipSuccess)
-    e = launch_cov_operands(cov->Q, n_samples, cov->n_pad, cov->q, cov->wop, cov->wop_hl, s);
+    e = launch_cov_operands(cov->Q, n_samples, cov->n_pad, cov->q, cov->wop_fp32, cov->wop_hl, s);
   int32_t hf[2] = {0, 0};
   if (e == hipSuccess) e = hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -488,7 +486,7 @@ extern "C" tgw_status tgw_plan_create(const tgw_panel* const* panels, int32_t n_
       }
     } else {
       ColBlock w{};
-      w.op = (const char*)p->cov->wop[wprec(pl->prec)];
+      w.op = (const char*)p->cov->wop_fp32;
       w.panel = j;
       w.col0 = j * kSlots;
       w.ncol = kSlots;
