@@ -176,8 +176,12 @@ struct BindArgs {
 };
 
 // ---- launchers (kernels.hip) -------------------------------------------------
+// covariate QR: row-parallel passes over kQrGrid workgroups; scratch holds
+// kQrScratch doubles (the partial sums and the per-step coefficients)
+constexpr int kQrGrid = 128;
+constexpr int kQrScratch = kQrGrid * kSlots + 2 * kSlots;
 hipError_t launch_qr(const double* C, int64_t ldc, int64_t n, int64_t n_pad, int q, double* X, double* Q,
-                     double* rdiag, int32_t* flags, hipStream_t s);
+                     double* rdiag, double* scratch, int32_t* flags, hipStream_t s);
 hipError_t launch_cov_operands(const double* Q, int64_t n, int64_t n_pad, int q, void* wop_fp32,
                                void* const* wop_hl, hipStream_t s);
 hipError_t launch_prep(const void* Y, int y_fp64, int64_t ldy, int64_t n, int64_t n_pad, int64_t P,

@@ -1,6 +1,6 @@
 // gfx950 kernels of the phenotype-panel linear association scan.
 //
-//  qr_kernel          FP64 Householder QR of [1 | C] -> Q (Methods 2.2: Q
+//  qr_*_kernel        FP64 Householder QR of [1 | C] -> Q (Methods 2.2: Q
 //                     spans the covariate space and has orthonormal columns)
 //  prep_kernel        Eq. 1 + column standardization, once per panel, FP64;
 //                     writes the contraction operand (FP32 or BF16 hi + lo)
@@ -318,168 +318,141 @@ __device__ inline float table_nlog10p(TabPtr tab, float at) {
 }
 
 // ---------------------------------------------------------------------------
-// covariate QR (one workgroup)
-// X is an (q x n_pad) column-major work copy of [1 | C]; on exit it holds the
-// Householder vectors; Q (q x n_pad) receives the orthonormal basis.
+// covariate QR: Householder reflections on the (q x n_pad) column-major work
+// copy X of [1 | C].  Each step is three launches: row-parallel partial dot
+// products (kQrGrid workgroups, one contiguous row range each), one small
+// workgroup that sums the partials in workgroup order and forms the
+// reflection's coefficients, and a row-parallel update; so every pass over
+// the samples is spread over the GPU.  On exit X holds the Householder
+// vectors and Q (q x n_pad) the orthonormal basis.  Fixed grid and fixed
+// summation order: the result is the same in every run.
 // ---------------------------------------------------------------------------
-constexpr int kQrThreads = 1024;
+constexpr int kQrThreads = 256;
+constexpr int kQrCB = 4;  // columns reduced together
 
-__global__ __launch_bounds__(kQrThreads) void qr_kernel(const double* __restrict__ C, int64_t ldc, int64_t n,
-                                                        int64_t n_pad, int q, double* __restrict__ X,
-                                                        double* __restrict__ Q, double* rdiag,
-                                                        int32_t* flags) {
-  __shared__ double vtv_s[kMaxCov + 1];
-  const int tid = threadIdx.x;
-  // load [1 | C]; pad rows are zero
+__global__ __launch_bounds__(kQrThreads) void qr_load_kernel(const double* __restrict__ C, int64_t ldc, int64_t n,
+                                                             int64_t n_pad, int q, double* __restrict__ X,
+                                                             int32_t* flags) {
+  const int64_t total = n_pad * q;
   int bad = 0;
-  for (int k = 0; k < q; ++k) {
-    for (int64_t i = tid; i < n_pad; i += kQrThreads) {
-      double v = 0.0;
-      if (i < n) {
-        v = (k == 0) ? 1.0 : C[(int64_t)(k - 1) * ldc + i];
-        if (!isfinite(v)) bad = 1;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int k = (int)(idx / n_pad);
+    const int64_t i = idx - (int64_t)k * n_pad;
+    double v = 0.0;  // pad rows are zero
+    if (i < n) {
+      v = (k == 0) ? 1.0 : C[(int64_t)(k - 1) * ldc + i];
+      if (!isfinite(v)) bad = 1;
+    }
+    X[idx] = v;
+  }
+  if (bad) flags[0] = 1;
+}
+
+// part[b][k] = sum over workgroup b's rows i >= i0 of v[i] * W[k][i], for
+// k0 <= k < q (zero for a workgroup with no such rows)
+__global__ __launch_bounds__(kQrThreads) void qr_dots_kernel(const double* __restrict__ v,
+                                                             const double* __restrict__ W, int64_t n,
+                                                             int64_t n_pad, int q, int k0, int64_t i0,
+                                                             double* __restrict__ part) {
+  __shared__ double sh[(kQrThreads / 64) * kQrCB];
+  const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+  int64_t rb = (int64_t)blockIdx.x * per;
+  const int64_t re = rb + per < n ? rb + per : n;
+  rb = rb > i0 ? rb : i0;
+  for (int c0 = k0; c0 < q; c0 += kQrCB) {
+    double d[kQrCB];
+#pragma unroll
+    for (int t = 0; t < kQrCB; ++t) d[t] = 0.0;
+    for (int64_t i = rb + threadIdx.x; i < re; i += kQrThreads) {
+      const double vi = v[i];
+#pragma unroll
+      for (int t = 0; t < kQrCB; ++t) {
+        const int64_t col = c0 + t < q ? c0 + t : q - 1;  // clamped: a valid address, value unused
+        d[t] += vi * W[col * n_pad + i];
       }
-      X[(int64_t)k * n_pad + i] = v;
+    }
+    block_sum_vec<kQrThreads, kQrCB>(d, sh);
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int t = 0; t < kQrCB; ++t)
+        if (c0 + t < q) part[(int64_t)blockIdx.x * kSlots + c0 + t] = d[t];
     }
   }
-  bad = __syncthreads_or(bad);
-  if (bad) {
-    if (tid == 0) flags[0] = 1;
-    return;
-  }
-  // Householder step j: passes over the rows below j gather ||x_j||^2 and
-  // x_j . x_k for the later columns k, CB columns a pass (their sums are
-  // reduced together); one pass then applies the reflection to all of them
-  constexpr int NQ = kMaxCov + 1, CB = 4;
-  __shared__ double shv[(kQrThreads / 64) * CB];
-  __shared__ double dv_s[NQ];
-  __shared__ double f_s[NQ];
-  // A thread takes its rows RPI at a time (i, i + kQrThreads, ...) and
-  // reads them for CB columns before it uses any of them, so that the loads
-  // of a pass are in flight together; a row past n is clamped to row i and a
-  // column past q - 1 to q - 1 (valid addresses whose values are not used).
-  // The order of the sums and updates per row is the plain one.
-  constexpr int RPI = 4;
-  struct Rows {
-    int64_t i[RPI];
-    bool ok[RPI];
-  };
-  auto rows_at = [&](int64_t i) {
-    Rows r;
-#pragma unroll
-    for (int u = 0; u < RPI; ++u) {
-      const int64_t ii = i + (int64_t)u * kQrThreads;
-      r.ok[u] = ii < n;
-      r.i[u] = r.ok[u] ? ii : i;
-    }
-    return r;
-  };
-  // dv_s[k] = sum over rows i >= i0 of v[i] * W[k][i], for j0 <= k < q
-  auto dots = [&](const double* v, const double* W, int j0, int64_t i0) {
-    for (int k0 = j0; k0 < q; k0 += CB) {
-      double d[CB];
-#pragma unroll
-      for (int t = 0; t < CB; ++t) d[t] = 0.0;
-#pragma unroll 1
-      for (int64_t i = i0 + tid; i < n; i += RPI * kQrThreads) {
-        const Rows r = rows_at(i);
-        double vv[RPI], w[RPI][CB];
-#pragma unroll
-        for (int u = 0; u < RPI; ++u) vv[u] = v[r.i[u]];
-#pragma unroll
-        for (int t = 0; t < CB; ++t) {
-          const int64_t col = (int64_t)(k0 + t < q ? k0 + t : q - 1) * n_pad;
-#pragma unroll
-          for (int u = 0; u < RPI; ++u) w[u][t] = W[col + r.i[u]];
-        }
-#pragma unroll
-        for (int t = 0; t < CB; ++t)
-#pragma unroll
-          for (int u = 0; u < RPI; ++u) {
-            const double e = d[t] + vv[u] * w[u][t];
-            d[t] = r.ok[u] ? e : d[t];
-          }
-      }
-      block_sum_vec<kQrThreads, CB>(d, shv);
-      if (tid == 0) {
-#pragma unroll
-        for (int t = 0; t < CB; ++t)
-          if (k0 + t < q) dv_s[k0 + t] = d[t];
-      }
-    }
-    __syncthreads();
-  };
-  // W[k][i] -= f_s[k] * v[i] for rows i >= i0 and k0 <= k < q
-  auto reflect = [&](const double* v, double* W, int k_begin, int64_t i0) {
-    for (int k0 = k_begin; k0 < q; k0 += CB) {
-#pragma unroll 1
-      for (int64_t i = i0 + tid; i < n; i += RPI * kQrThreads) {
-        const Rows r = rows_at(i);
-        double vv[RPI], w[RPI][CB];
-#pragma unroll
-        for (int u = 0; u < RPI; ++u) vv[u] = v[r.i[u]];
-#pragma unroll
-        for (int t = 0; t < CB; ++t) {
-          const int64_t col = (int64_t)(k0 + t < q ? k0 + t : q - 1) * n_pad;
-#pragma unroll
-          for (int u = 0; u < RPI; ++u) w[u][t] = W[col + r.i[u]];
-        }
-#pragma unroll
-        for (int t = 0; t < CB; ++t) {
-          if (k0 + t < q) {
-            const int64_t col = (int64_t)(k0 + t) * n_pad;
-            const double f = f_s[k0 + t];
-#pragma unroll
-            for (int u = 0; u < RPI; ++u)
-              if (r.ok[u]) W[col + r.i[u]] = w[u][t] - f * vv[u];
-          }
-        }
-      }
-    }
-  };
-  for (int j = 0; j < q; ++j) {
-    double* xj = X + (int64_t)j * n_pad;
-    dots(xj, X, j, j + 1);  // dv_s[j]: squares below row j; dv_s[k > j]: dots below row j
-    if (tid == 0) {
-      const double xjj = xj[j];
-      const double below = dv_s[j];
-      const double nrm = sqrt(xjj * xjj + below);
-      const double alpha = xjj > 0.0 ? -nrm : nrm;
-      const double v0 = xjj - alpha;
-      const double vtv = below + v0 * v0;
-      xj[j] = v0;
-      rdiag[j] = alpha;
-      vtv_s[j] = vtv;
-      for (int k = j + 1; k < q; ++k)
-        f_s[k] = vtv > 0.0 ? 2.0 * (dv_s[k] + v0 * X[(int64_t)k * n_pad + j]) / vtv : 0.0;
-    }
-    __syncthreads();
-    reflect(xj, X, j + 1, j);
-    __syncthreads();
-  }
-  // Q = H_0 ... H_{q-1} [I_q; 0], the reflections applied from the last
-  for (int k = 0; k < q; ++k)
-    for (int64_t i = tid; i < n_pad; i += kQrThreads) Q[(int64_t)k * n_pad + i] = (i == k) ? 1.0 : 0.0;
+}
+
+// step j's sums dv[k] (k >= j) from the partials, then the coefficients.
+// forward: dv[j] = squares of x_j below row j, dv[k > j] = x_j . x_k below
+// row j; the reflection maps x_j to alpha e_j (rdiag[j] = alpha), v_j = x_j
+// with v_j[j] = x_j[j] - alpha, and fv[k] = 2 (v_j . x_k) / (v_j . v_j).
+// backward (forming Q): dv[k] = v_j . Q_k from row j on, fv[k] = 2 dv[k] / vtv[j].
+// (one workgroup of kQrThreads; the partials are staged in LDS with
+// coalesced loads, then lane k sums column k's in workgroup order)
+__global__ __launch_bounds__(kQrThreads) void qr_coef_kernel(double* X, int64_t n_pad, int q, int j, int forward,
+                                                             const double* __restrict__ part, double* rdiag,
+                                                             double* fv, double* vtv) {
+  __shared__ double ps[kQrGrid * kSlots];
+  __shared__ double dv[kSlots];
+  for (int idx = threadIdx.x; idx < kQrGrid * kSlots; idx += kQrThreads) ps[idx] = part[idx];
   __syncthreads();
-  for (int j = q - 1; j >= 0; --j) {
-    const double* xj = X + (int64_t)j * n_pad;
-    dots(xj, Q, j, j);
-    if (tid == 0) {
-      const double vtv = vtv_s[j];
-      for (int k = j; k < q; ++k) f_s[k] = vtv > 0.0 ? 2.0 * dv_s[k] / vtv : 0.0;
-    }
-    __syncthreads();
-    reflect(xj, Q, j, j);
-    __syncthreads();
+  const int k = threadIdx.x;
+  if (k >= j && k < q) {
+    double s = 0.0;
+    for (int b = 0; b < kQrGrid; ++b) s += ps[b * kSlots + k];
+    dv[k] = s;
   }
-  if (tid == 0) {
-    double mx = 0.0;
-    for (int j = 0; j < q; ++j) mx = fmax(mx, fabs(rdiag[j]));
-    int rd = 0;
-    for (int j = 0; j < q; ++j)
-      if (!(fabs(rdiag[j]) > 1e-10 * mx)) rd = 1;
-    flags[1] = rd;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  if (forward) {
+    double* xj = X + (int64_t)j * n_pad;
+    const double xjj = xj[j];
+    const double below = dv[j];
+    const double nrm = sqrt(xjj * xjj + below);
+    const double alpha = xjj > 0.0 ? -nrm : nrm;
+    const double v0 = xjj - alpha;
+    const double t = below + v0 * v0;
+    xj[j] = v0;
+    rdiag[j] = alpha;
+    vtv[j] = t;
+    for (int c = j + 1; c < q; ++c) fv[c] = t > 0.0 ? 2.0 * (dv[c] + v0 * X[(int64_t)c * n_pad + j]) / t : 0.0;
+  } else {
+    const double t = vtv[j];
+    for (int c = j; c < q; ++c) fv[c] = t > 0.0 ? 2.0 * dv[c] / t : 0.0;
   }
+}
+
+// W[k][i] -= fv[k] * v[i] for rows i0 <= i < n and k0 <= k < q
+__global__ __launch_bounds__(kQrThreads) void qr_reflect_kernel(const double* v, double* W, int64_t n, int64_t n_pad,
+                                                                int q, int k0, int64_t i0,
+                                                                const double* __restrict__ fv) {
+  __shared__ double f_s[kSlots];
+  if (threadIdx.x < kSlots) f_s[threadIdx.x] = (int)threadIdx.x >= k0 && (int)threadIdx.x < q ? fv[threadIdx.x] : 0.0;
+  __syncthreads();
+  for (int64_t i = i0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double vi = v[i];
+    for (int k = k0; k < q; ++k) W[(int64_t)k * n_pad + i] -= f_s[k] * vi;
+  }
+}
+
+// Q = [I_q; 0] before the reflections are applied from the last
+__global__ void qr_qinit_kernel(double* Q, int64_t n_pad, int q) {
+  const int64_t total = n_pad * q;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int k = (int)(idx / n_pad);
+    Q[idx] = (idx - (int64_t)k * n_pad == k) ? 1.0 : 0.0;
+  }
+}
+
+// rank check: every |R_jj| above 1e-10 max |R_ii|
+__global__ void qr_rank_kernel(const double* rdiag, int q, int32_t* flags) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double mx = 0.0;
+  for (int j = 0; j < q; ++j) mx = fmax(mx, fabs(rdiag[j]));
+  int rd = 0;
+  for (int j = 0; j < q; ++j)
+    if (!(fabs(rdiag[j]) > 1e-10 * mx)) rd = 1;
+  flags[1] = rd;
 }
 
 
@@ -2386,8 +2359,27 @@ hipError_t launch_gemm(int idx, int prec, int mode, const GemmArgs& a, int grid,
 }
 
 hipError_t launch_qr(const double* C, int64_t ldc, int64_t n, int64_t n_pad, int q, double* X, double* Q,
-                     double* rdiag, int32_t* flags, hipStream_t s) {
-  hipLaunchKernelGGL(qr_kernel, dim3(1), dim3(kQrThreads), 0, s, C, ldc, n, n_pad, q, X, Q, rdiag, flags);
+                     double* rdiag, double* scratch, int32_t* flags, hipStream_t s) {
+  if (q < 1 || q > kSlots) return hipErrorInvalidValue;
+  double* part = scratch;
+  double* fv = scratch + kQrGrid * kSlots;
+  double* vtv = fv + kSlots;
+  const dim3 g(kQrGrid), b(kQrThreads);
+  hipLaunchKernelGGL(qr_load_kernel, g, b, 0, s, C, ldc, n, n_pad, q, X, flags);
+  for (int j = 0; j < q; ++j) {
+    const double* xj = X + (int64_t)j * n_pad;
+    hipLaunchKernelGGL(qr_dots_kernel, g, b, 0, s, xj, (const double*)X, n, n_pad, q, j, (int64_t)j + 1, part);
+    hipLaunchKernelGGL(qr_coef_kernel, dim3(1), b, 0, s, X, n_pad, q, j, 1, (const double*)part, rdiag, fv, vtv);
+    if (j + 1 < q) hipLaunchKernelGGL(qr_reflect_kernel, g, b, 0, s, xj, X, n, n_pad, q, j + 1, (int64_t)j, (const double*)fv);
+  }
+  hipLaunchKernelGGL(qr_qinit_kernel, g, b, 0, s, Q, n_pad, q);
+  for (int j = q - 1; j >= 0; --j) {
+    const double* xj = X + (int64_t)j * n_pad;
+    hipLaunchKernelGGL(qr_dots_kernel, g, b, 0, s, xj, (const double*)Q, n, n_pad, q, j, (int64_t)j, part);
+    hipLaunchKernelGGL(qr_coef_kernel, dim3(1), b, 0, s, X, n_pad, q, j, 0, (const double*)part, rdiag, fv, vtv);
+    hipLaunchKernelGGL(qr_reflect_kernel, g, b, 0, s, xj, Q, n, n_pad, q, j, (int64_t)j, (const double*)fv);
+  }
+  hipLaunchKernelGGL(qr_rank_kernel, dim3(1), dim3(64), 0, s, (const double*)rdiag, q, flags);
   return hipGetLastError();
 }
 

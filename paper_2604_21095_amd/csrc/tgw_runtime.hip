@@ -203,22 +203,24 @@ extern "C" tgw_status tgw_fit_covariates(int64_t n_samples, int32_t n_cov, const
   cov->n_pad = round_up(n_samples, kChunk);
   cov->q = n_cov + 1;
   cov->n_chunks = (int)(cov->n_pad / kChunk);
-  double *X = nullptr, *rdiag = nullptr;
+  double *X = nullptr, *rdiag = nullptr, *qrs = nullptr;
   int32_t* flags = nullptr;
   auto cleanup = [&]() {
     (void)hipFree(X);
     (void)hipFree(rdiag);
+    (void)hipFree(qrs);
     (void)hipFree(flags);
   };
   hipError_t e = dmalloc(&cov->Q, (size_t)cov->q * cov->n_pad);
   if (e == hipSuccess) e = dmalloc(&X, (size_t)cov->q * cov->n_pad);
   if (e == hipSuccess) e = dmalloc(&rdiag, (size_t)cov->q);
+  if (e == hipSuccess) e = dmalloc(&qrs, (size_t)kQrScratch);
   if (e == hipSuccess) e = dmalloc(&flags, 2);
   if (e == hipSuccess) e = hipMalloc(&cov->wop_fp32, (size_t)cov->n_chunks * kBlockBytes);
   for (int k : {(int)kSplit, (int)kSplit16})
     if (e == hipSuccess) e = hipMalloc(&cov->wop_hl[k], (size_t)hl_blocks(cov->q) * cov->n_chunks * kBlockBytes);
   if (e == hipSuccess) e = hipMemsetAsync(flags, 0, 2 * sizeof(int32_t), s);
-  if (e == hipSuccess) e = launch_qr(d_C, ldc, n_samples, cov->n_pad, cov->q, X, cov->Q, rdiag, flags, s);
+  if (e == hipSuccess) e = launch_qr(d_C, ldc, n_samples, cov->n_pad, cov->q, X, cov->Q, rdiag, qrs, flags, s);
   if (e == hipSuccess)
     e = launch_cov_operands(cov->Q, n_samples, cov->n_pad, cov->q, cov->wop_fp32, cov->wop_hl, s);
   int32_t hf[2] = {0, 0};
