@@ -228,6 +228,43 @@ def test_plink_coding_and_k31(tgw, precision):
     compare(res[0], ref, ref["df"], f"plink K=31 {precision} ")
 
 
+@pytest.mark.parametrize("n,k", [(34, 31), (40, 5), (500, 10), (23_000, 10)])
+def test_covariate_basis(tgw, n, k):
+    """Q of [1 | C] (Eq. 1) against numpy's Householder QR: orthonormal
+    columns that rebuild [1 | C], equal to numpy's up to column signs; two
+    fits give the same bits (fixed grid and summation order). At n = 34 and
+    40 most of the row-parallel workgroups get no rows."""
+    say(f"case: covariate basis n={n} K={k}")
+    rng = np.random.default_rng(1000 + n + k)
+    C = rng.standard_normal((n, k))
+    X = np.hstack([np.ones((n, 1)), C])
+    Q1 = tgw.fit_covariates(torch.from_numpy(C).cuda()).Q()
+    Q2 = tgw.fit_covariates(torch.from_numpy(C).cuda()).Q()
+    torch.cuda.synchronize()
+    assert torch.equal(Q1, Q2)
+    Q = Q1.cpu().numpy()
+    assert np.abs(Q.T @ Q - np.eye(k + 1)).max() < 1e-11
+    assert np.abs(X - Q @ (Q.T @ X)).max() < 1e-10 * np.abs(X).max()
+    Qn, _ = np.linalg.qr(X)
+    assert np.abs(np.abs(Q.T @ Qn) - np.eye(k + 1)).max() < 1e-10
+
+
+def test_tiny_cohort(tgw):
+    """A 40-sample cohort (one 64-sample chunk, most QR workgroups idle) in
+    every precision against the oracle."""
+    n, m, k = 40, 300, 5
+    say(f"case: tiny cohort n={n}")
+    rng = np.random.default_rng(40)
+    codes = rng.choice(4, size=(m, n), p=[0.3, 0.4, 0.25, 0.05]).astype(np.uint8)
+    C = rng.standard_normal((n, k))
+    Y = (rng.standard_normal((n, 9)) + C[:, :2] @ rng.standard_normal((2, 9))).astype(np.float32)
+    packed = pack_codes_np(codes, row_bytes_for(n))
+    ref = oracle_scan(codes, C, Y)
+    for precision in PRECS:
+        res, _, _ = gpu_scan(C, [Y], packed, precision)
+        compare(res[0], ref, ref["df"], f"tiny n={n} {precision} ")
+
+
 @pytest.mark.parametrize("precision", PRECS)
 def test_tail_fp64(tgw, precision):
     """|t| > 40 goes through the FP64 tail kernel."""
