@@ -171,6 +171,8 @@ tgw_status tgw_init(void);
 /* ---- covariates (paper Methods 2.2, Eq. 1: Q spans the covariate space) --
  * Builds Q (n_samples x q, q = n_cov + 1, orthonormal columns) by an FP64
  * Householder QR of X0 = [1 | C] on the GPU.  The intercept is always added.
+ * The reductions run over a fixed grid in a fixed order, so the same C gives
+ * the same Q bit for bit in every call.
  *   d_C   device FP64, column-major n_samples x n_cov, leading dim ldc >= n_samples
  *         (may be NULL when n_cov == 0).  Not retained.
  * Synchronizes `stream` once to report:
