@@ -34,6 +34,7 @@ from .assoc import (  # noqa: F401
     decode,
     decode_dosage8,
     impute_mean,
+    marker_is_valid,
     prepare_panel,
     residual_df,
     scan,

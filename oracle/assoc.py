@@ -135,6 +135,17 @@ def prepare_panel(Y: np.ndarray, Q: np.ndarray):
     return Yt, s, valid
 
 
+def marker_is_valid(n_obs: np.ndarray, mono: np.ndarray, h2: np.ndarray, gc2: np.ndarray) -> np.ndarray:
+    """Which markers are tested (a reading: the paper does not say).
+
+    A marker is tested when it has at least one observed call, its observed
+    calls are not all equal, and the covariate projection leaves more than
+    MARKER_TOL of its centred sum of squares (h2 > MARKER_TOL * gc2); a marker
+    inside the covariate span has no residual variation to correlate.
+    """
+    return (n_obs > 0) & ~mono & (h2 > MARKER_TOL * gc2)
+
+
 def residual_df(n_samples: int, q: int) -> int:
     """Residual degrees of freedom of y ~ [Q | g]: N - q - 1."""
     return n_samples - q - 1
@@ -165,7 +176,7 @@ def scan(G: np.ndarray, C: np.ndarray, Y: np.ndarray, Q: np.ndarray = None):
     gc2 = np.einsum("ij,ij->i", G_c, G_c)
     G_res = G_imp - (G_imp @ Q) @ Q.T
     h2 = np.einsum("ij,ij->i", G_res, G_res)
-    mvalid = (n_obs > 0) & ~mono & (h2 > MARKER_TOL * gc2)
+    mvalid = marker_is_valid(n_obs, mono, h2, gc2)
     h = np.sqrt(h2)
 
     with np.errstate(invalid="ignore", divide="ignore"):

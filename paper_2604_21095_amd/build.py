@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libtgw.so")
 SOURCES = [os.path.join(HERE, "csrc", f) for f in ("tgw_kernels.hip", "tgw_runtime.hip", "tgw_bed.hip")]
-HEADER = os.path.join(ROOT, "include", "tgw.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("tgw.h", "tgw_debug.h")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
@@ -43,7 +43,8 @@ def build(verbose: bool = False) -> str:
     os.replace(tmp, LIB)
     cc = shutil.which("gcc") or shutil.which("cc")
     if cc:
-        subprocess.run([cc, "-std=c99", "-Wall", "-Werror", "-fsyntax-only", "-x", "c", HEADER], check=True)
+        for h in HEADERS:
+            subprocess.run([cc, "-std=c99", "-Wall", "-Werror", "-fsyntax-only", "-x", "c", h], check=True)
     return LIB
 
 

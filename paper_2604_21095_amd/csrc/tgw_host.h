@@ -4,6 +4,7 @@
 #pragma once
 
 #include "../../include/tgw.h"
+#include "../../include/tgw_debug.h"
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>

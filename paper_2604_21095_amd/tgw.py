@@ -16,7 +16,8 @@ import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtgw.so")
-HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "tgw.h")
+INCLUDE_DIR = os.path.join(os.path.dirname(_HERE), "include")
+HEADER_PATH = os.path.join(INCLUDE_DIR, "tgw.h")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} not built; run paper_2604_21095_amd/build.py (or __graft_entry__.build())")
@@ -141,10 +142,14 @@ def status_string(status: int) -> str:
 
 
 def header_symbols() -> List[str]:
-    """Every function declared in include/tgw.h."""
-    text = open(HEADER_PATH).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(tgw_\w+)\s*\(", text)))
+    """Every function declared in the headers under include/ (tgw.h, tgw_debug.h)."""
+    names = set()
+    for fn in sorted(os.listdir(INCLUDE_DIR)):
+        if fn.endswith(".h"):
+            text = open(os.path.join(INCLUDE_DIR, fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names.update(re.findall(r"\b(tgw_\w+)\s*\(", text))
+    return sorted(names)
 
 
 def _stream(stream) -> ctypes.c_void_p:

@@ -9,6 +9,11 @@ if ROOT not in sys.path:
 
 
 def pytest_configure(config):
+    # plans take their tile shape from the autotuner's cache; a fresh cache per
+    # session keeps the shape each test runs independent of what a host's
+    # ~/.cache holds (tests that tune point the library at their own file)
+    import tempfile
+    os.environ["TGW_TUNE_CACHE"] = os.path.join(tempfile.mkdtemp(prefix="tgw_tune_"), "tune.json")
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: long-running CPU test")
 

@@ -29,10 +29,18 @@ def test_header_is_plain_c(tmp_path):
     if not cc:
         pytest.skip("no C compiler")
     src = tmp_path / "use.c"
-    src.write_text('#include "tgw.h"\nint main(void) { tgw_outputs o = {0}; (void)o; '
+    src.write_text('#include "tgw.h"\n#include "tgw_debug.h"\nint main(void) { tgw_outputs o = {0}; (void)o; '
                    'return (int)tgw_abi_version() - TGW_ABI_VERSION; }\n')
     subprocess.run([cc, "-std=c99", "-Wall", "-Werror", "-pedantic", "-fsyntax-only", "-I",
                     os.path.dirname(HEADER), str(src)], check=True)
+
+
+def test_test_hooks_stay_out_of_the_product_header(tgw):
+    text = open(HEADER).read()
+    assert "tgw_debug_" not in text
+    dbg = open(os.path.join(os.path.dirname(HEADER), "tgw_debug.h")).read()
+    for name in ("tgw_debug_contract", "tgw_debug_set_operand", "tgw_debug_marker_stats"):
+        assert name in dbg and name in tgw.header_symbols()
 
 
 def test_status_strings(tgw):

@@ -24,6 +24,18 @@ def _tiny_cohort(rng, n, k, m, p, miss):
     return G, C, Y
 
 
+def _nanmean_impute(G):
+    """Mean imputation written out here with numpy's nanmean, row by row, so
+    that the least-squares pins do not take the oracle's own imputation."""
+    G = np.array(G, dtype=np.float64)
+    for m in range(G.shape[0]):
+        row = G[m]
+        miss = np.isnan(row)
+        if miss.any() and not miss.all():
+            row[miss] = np.nanmean(row)
+    return G
+
+
 def _brute_ols(g, C, y):
     """OLS of y on [1, C, g] by least squares; returns beta, se, t, df."""
     n = len(y)
@@ -44,7 +56,7 @@ def test_brute_force_ols(n, k, miss):
     rng = np.random.default_rng(1000 + n + k)
     G, C, Y = _tiny_cohort(rng, n, k, 20, 3, miss)
     out = oracle.scan(G, C, Y)
-    G_imp, _, _ = oracle.impute_mean(G)
+    G_imp = _nanmean_impute(G)
     assert out["df"] == n - k - 2
     checked = 0
     for m in range(G.shape[0]):
@@ -247,7 +259,7 @@ def test_brute_force_ols_fractional_dosages():
     G = oracle.decode_dosage8(q, n)
     out = oracle.scan(G, C, Y)
     assert not out["marker_valid"][0] and np.all(np.isnan(out["t"][0]))
-    G_imp, _, _ = oracle.impute_mean(G)
+    G_imp = _nanmean_impute(G)
     checked = 0
     for m in range(1, G.shape[0]):
         assert out["marker_valid"][m]
@@ -277,6 +289,58 @@ def test_degenerate_markers_and_phenotypes():
     assert np.all(np.isnan(out["r"][:3]))
     assert np.all(np.isnan(out["t"][:, 1]))
     assert np.all(np.isfinite(out["t"][3:, [0, 2]]))
+
+
+def _span_residual(v, C):
+    """v minus its least-squares fit on [1 | C] (numpy lstsq, not a QR)."""
+    X = np.column_stack([np.ones(len(v)), C])
+    coef, _, _, _ = np.linalg.lstsq(X, v, rcond=None)
+    return v - X @ coef
+
+
+# ratio h^2 / ||g_c||^2 of each planted marker; the oracle tests a marker only
+# above MARKER_TOL = 1e-8 (reading R10)
+SPAN_RATIOS = (0.0, 0.0, 0.67e-8, 1.5e-8, 1e-6, 1e-4, 1e-2)
+
+
+def test_markers_near_the_covariate_span():
+    """Conditional analysis puts a lead marker's dosage among the covariates:
+    that marker (and its allele flip) lies in the covariate span and gives
+    NaN; markers a distance eps off the span keep exactly the planted share
+    h^2 / ||g_c||^2 of their variance.  Below the threshold: NaN; above: the
+    least-squares fit of y ~ 1 + C + g."""
+    rng = np.random.default_rng(2024)
+    n, k = 240, 3
+    C0 = rng.standard_normal((n, k))
+    lead = rng.binomial(2, 0.3, n).astype(np.float64)
+    C = np.column_stack([C0, lead])
+    Y = rng.standard_normal((n, 3)) + 0.4 * lead[:, None] + C0 @ rng.standard_normal((k, 3))
+    Y[:, 2] += 0.5 * rng.standard_normal(n)
+    z = _span_residual(rng.standard_normal(n), C)      # orthogonal to 1 and C
+    lead_c = lead - lead.mean()
+    rows = [lead, 2.0 - lead]
+    for rho in SPAN_RATIOS[2:]:
+        eps = math.sqrt(rho / (1.0 - rho)) * np.linalg.norm(lead_c) / np.linalg.norm(z)
+        rows.append(lead + eps * z)
+    G = np.array(rows)
+    # the planted ratio, measured by lstsq residuals and plain centring
+    for m, rho in enumerate(SPAN_RATIOS):
+        h2 = np.sum(_span_residual(G[m], C) ** 2)
+        gc2 = np.sum((G[m] - G[m].mean()) ** 2)
+        assert abs(h2 / gc2 - rho) <= 1e-3 * rho + 1e-14, (m, h2 / gc2, rho)
+    out = oracle.scan(G, C, Y)
+    for m, rho in enumerate(SPAN_RATIOS):
+        for name in ("r", "beta", "se", "t", "nlog10p"):
+            if rho <= 1e-8:
+                assert np.all(np.isnan(out[name][m])), (m, name)
+            else:
+                assert np.all(np.isfinite(out[name][m])), (m, name)
+        if rho > 1e-8:
+            for p in range(Y.shape[1]):
+                beta, se, t, df = _brute_ols(G[m], C, Y[:, p])
+                np.testing.assert_allclose(out["t"][m, p], t, rtol=1e-6, atol=1e-8)
+                np.testing.assert_allclose(out["beta"][m, p], beta, rtol=1e-6)
+                np.testing.assert_allclose(out["se"][m, p], se, rtol=1e-6)
 
 
 def test_errors():
@@ -319,3 +383,46 @@ def test_planted_mistake_unresidualized_genotype_is_caught(monkeypatch):
     monkeypatch.setattr(oracle, "scan", no_g_resid)
     with pytest.raises(AssertionError):
         test_brute_force_ols(200, 4, 0.05)
+
+
+def test_planted_mistake_zero_imputation_is_caught(monkeypatch):
+    def zero_fill(G):
+        obs = ~np.isnan(G)
+        n_obs = obs.sum(axis=1)
+        with np.errstate(invalid="ignore", divide="ignore"):
+            mu = np.where(obs, G, 0.0).sum(axis=1) / n_obs
+        return np.where(obs, G, 0.0), n_obs, mu
+
+    monkeypatch.setattr(assoc, "impute_mean", zero_fill)
+    with pytest.raises(AssertionError):
+        test_brute_force_ols(50, 1, 0.2)
+
+
+def test_planted_mistake_median_imputation_is_caught(monkeypatch):
+    def median_fill(G):
+        obs = ~np.isnan(G)
+        n_obs = obs.sum(axis=1)
+        with np.errstate(invalid="ignore", divide="ignore"):
+            mu = np.where(obs, G, 0.0).sum(axis=1) / n_obs
+        med = np.nanmedian(G, axis=1)
+        return np.where(obs, G, med[:, None]), n_obs, mu
+
+    monkeypatch.setattr(assoc, "impute_mean", median_fill)
+    with pytest.raises(AssertionError):
+        test_brute_force_ols(200, 4, 0.05)
+
+
+def test_planted_mistake_reversed_marker_rule_is_caught(monkeypatch):
+    def reversed_rule(n_obs, mono, h2, gc2):
+        return (n_obs > 0) & ~mono & (h2 < assoc.MARKER_TOL * gc2)
+
+    monkeypatch.setattr(assoc, "marker_is_valid", reversed_rule)
+    with pytest.raises(AssertionError):
+        test_markers_near_the_covariate_span()
+
+
+@pytest.mark.parametrize("tol", [0.0, 1e-4])
+def test_planted_mistake_marker_threshold_is_caught(monkeypatch, tol):
+    monkeypatch.setattr(assoc, "MARKER_TOL", tol)
+    with pytest.raises(AssertionError):
+        test_markers_near_the_covariate_span()
