@@ -23,8 +23,9 @@
  * Conventions
  *   - "device" pointers point to memory on the current HIP device; the caller
  *     owns every buffer it passes in (covariates, phenotypes, genotypes,
- *     outputs).  Handles own their device memory (allocated with hipMalloc at
- *     creation) and free it in tgw_*_free.
+ *     outputs).  Handles own their device memory, taken at creation from the
+ *     registered allocator (tgw_set_allocator; default hipMalloc), and give
+ *     it back in tgw_*_free.
  *   - "stream" is a hipStream_t passed as void*; NULL means the default stream.
  *   - All functions return a tgw_status; TGW_OK is 0.  On error nothing is
  *     enqueued and tgw_last_error() gives a thread-local message.  C++
@@ -41,7 +42,7 @@
 extern "C" {
 #endif
 
-#define TGW_ABI_VERSION 4
+#define TGW_ABI_VERSION 5
 
 typedef enum {
   TGW_OK = 0,
@@ -62,8 +63,13 @@ typedef enum {
  *  TGW_PREC_FP32      : FP32 operands on the FP32 matrix cores, FP32 accumulate.
  *  TGW_PREC_SPLIT     : the prepared panel is split into BF16 hi + lo terms
  *                       (relative residual <= 2^-16); the genotype operand is
- *                       exact in BF16 (calls re-centred by c = round(64 mu)/64,
- *                       missing calls carry mu - c to within 2^-16); two BF16
+ *                       exact in BF16: a call g enters as gs (g - c) with a
+ *                       per-marker scale gs = K / 128 and c = U / K (K, U
+ *                       integers, 1 <= K <= 256, chosen per marker so that
+ *                       the missing value gs (mu - c) rounds to BF16 with
+ *                       the least error), a missing call as gs (mu - c) to
+ *                       within about 2^-9 |mu - c| (at most about 2^-18,
+ *                       typically below 2^-24, in genotype units); two BF16
  *                       matrix-core passes, FP32 accumulate.
  *  TGW_PREC_SPLIT_F16 : the same with FP16 hi + lo terms (panel scaled by 2^12
  *                       before the split, relative residual <= 2^-22) and
@@ -161,6 +167,29 @@ typedef struct {
   int32_t reserved;
 } tgw_plan_options;
 
+/* ---- device memory ---------------------------------------------------------
+ * The phenotype panel is prepared once and its operand, like the covariate
+ * basis and the scan workspace, stays resident on the device (Methods 2.1:
+ * preprocessing is reused across the panel).  That memory, and the temporary
+ * buffers of tgw_fit_covariates and tgw_prepare_phenotypes, comes from the
+ * allocator registered here, so that a framework's caching allocator can
+ * supply it:
+ *   alloc_fn(bytes, stream, ctx) returns device memory of the current device,
+ *     aligned to at least 256 bytes, or NULL (-> TGW_ERR_OUT_OF_MEMORY);
+ *     `stream` is the hipStream_t of the call that allocates (NULL for
+ *     tgw_plan_create and the .bed streamer);
+ *   free_fn(ptr, stream, ctx) takes it back; the library has synchronized
+ *     the device before, so no enqueued work still uses it.
+ * Both NULL restores hipMalloc / hipFree; exactly one NULL is
+ * TGW_ERR_INVALID_ARG.  A handle keeps the allocator (and ctx) registered
+ * when it was made and frees through it, so ctx must outlive the handles
+ * made under it.  The functions are called on the thread of the tgw call
+ * that needs memory, never from inside a kernel or a stream callback.
+ * Thread-safe; applies to handles made after the call. */
+typedef void* (*tgw_alloc_fn)(size_t bytes, void* stream, void* ctx);
+typedef void (*tgw_free_fn)(void* ptr, void* stream, void* ctx);
+tgw_status tgw_set_allocator(tgw_alloc_fn alloc_fn, tgw_free_fn free_fn, void* ctx);
+
 /* ---- library ---------------------------------------------------------- */
 const char* tgw_status_string(tgw_status s);
 const char* tgw_last_error(void);      /* thread-local detail of the last error */
@@ -236,10 +265,11 @@ tgw_status tgw_plan_autotune(tgw_plan* plan, const uint8_t* d_geno, int64_t n_ma
  *              ignored.
  *   outs       n_panels entries, in the plan's panel order (see tgw_outputs).
  * Per marker: exact integer counts give the mean mu; each call g is fed to
- * the matrix cores as g - c with c = round(64 mu)/64 (exact in BF16 and FP32),
- * a missing call as mu - c rounded to the operand type (error <= 2^-16 in
- * BF16, 2^-21 in FP16); the intercept of the covariate projection removes c
- * exactly.  8-bit dosages enter as q - c with the integer c = round(mu) in
+ * the matrix cores as gs (g - c), exact in the operand type (FP32: gs = 1,
+ * c = round(64 mu)/64; FP16 forms: gs = 1, c = round(512 mu)/512; BF16: see
+ * TGW_PREC_SPLIT), a missing call as gs (mu - c) rounded to the operand type
+ * (error <= about 2^-18 in BF16, 2^-21 in FP16); the intercept of the
+ * covariate projection removes c exactly and the epilogue divides by gs.  8-bit dosages enter as q - c with the integer c = round(mu) in
  * units of 1/127 (exact in FP16 and FP32), a missing one as mu - c (error <=
  * 2^-12 / 127 in FP16).  They run the register-staged tile shapes; the
  * autotuner keeps a separate choice for them.

@@ -116,6 +116,7 @@ bool pread_parallel(int fd, uint8_t* dst, int64_t len, int64_t off, int n_thread
 }  // namespace
 
 struct tgw_bed {
+  DevAllocator mem;  // the allocator of its device buffers (registered at the first tgw_scan_bed)
   int fd = -1;
   int64_t n_file = 0, n_markers = 0, raw_bytes = 0;
   std::vector<int32_t> sel;  // file sample of each scan sample, in scan order
@@ -136,20 +137,21 @@ struct tgw_bed {
 };
 
 static void release_stream_state(tgw_bed* b) {
+  dev_release_begin(b->mem);
   for (auto& s : b->slot) {
     if (s.pending) {
       (void)hipEventSynchronize(s.copied);
       (void)hipEventSynchronize(s.used);
     }
     if (s.host) (void)hipHostFree(s.host);
-    if (s.draw) (void)hipFree(s.draw);
-    if (s.dpack) (void)hipFree(s.dpack);
+    dev_free(b->mem, s.draw, nullptr);
+    dev_free(b->mem, s.dpack, nullptr);
     if (s.copied) (void)hipEventDestroy(s.copied);
     if (s.used) (void)hipEventDestroy(s.used);
     s = tgw_bed::Slot{};
   }
   if (b->copy) (void)hipStreamDestroy(b->copy);
-  if (b->d_sel) (void)hipFree(b->d_sel);
+  dev_free(b->mem, b->d_sel, nullptr);
   b->copy = nullptr;
   b->d_sel = nullptr;
   b->sel_dirty = true;
@@ -320,14 +322,15 @@ extern "C" tgw_status tgw_scan_bed(tgw_plan* pl, tgw_bed* b, int64_t m_begin, in
   // streaming buffers
   if (b->device != dev || b->block != B || b->row_bytes != row_bytes) {
     release_stream_state(b);
+    b->mem = current_allocator();
     b->device = dev;
     b->block = B;
     b->row_bytes = row_bytes;
     hipError_t e = hipStreamCreateWithFlags(&b->copy, hipStreamNonBlocking);
     for (auto& sl : b->slot) {
       if (e == hipSuccess) e = hipHostMalloc((void**)&sl.host, (size_t)(B * b->raw_bytes), hipHostMallocDefault);
-      if (e == hipSuccess) e = hipMalloc((void**)&sl.draw, (size_t)(B * b->raw_bytes));
-      if (e == hipSuccess) e = hipMalloc((void**)&sl.dpack, (size_t)(B * row_bytes));
+      if (e == hipSuccess) e = dev_alloc(b->mem, (void**)&sl.draw, (size_t)(B * b->raw_bytes), nullptr);
+      if (e == hipSuccess) e = dev_alloc(b->mem, (void**)&sl.dpack, (size_t)(B * row_bytes), nullptr);
       if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.copied, hipEventDisableTiming);
       if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.used, hipEventDisableTiming);
     }
@@ -339,9 +342,10 @@ extern "C" tgw_status tgw_scan_bed(tgw_plan* pl, tgw_bed* b, int64_t m_begin, in
   if (b->sel_dirty) {
     for (auto& sl : b->slot)
       if (sl.pending) HIP_TRY(hipEventSynchronize(sl.used));  // the old selection may still be read
-    if (b->d_sel) HIP_TRY(hipFree(b->d_sel));
+    dev_release_begin(b->mem);
+    dev_free(b->mem, b->d_sel, nullptr);
     b->d_sel = nullptr;
-    HIP_TRY(hipMalloc((void**)&b->d_sel, (size_t)n_sel * sizeof(int32_t)));
+    HIP_TRY(dev_alloc(b->mem, (void**)&b->d_sel, (size_t)n_sel * sizeof(int32_t), nullptr));
     HIP_TRY(hipMemcpy(b->d_sel, b->sel.data(), (size_t)n_sel * sizeof(int32_t), hipMemcpyHostToDevice));
     b->sel_dirty = false;
   }

@@ -16,6 +16,21 @@ namespace tgw {
 tgw_status fail(tgw_status s, const std::string& msg);
 tgw_status hip_fail(hipError_t e, const char* what);
 
+// Device memory of the handles: the allocator registered with
+// tgw_set_allocator when a handle is made (alloc NULL: hipMalloc / hipFree).
+// A handle keeps the one it was made with and frees through it.
+struct DevAllocator {
+  tgw_alloc_fn alloc = nullptr;
+  tgw_free_fn free = nullptr;
+  void* ctx = nullptr;
+};
+DevAllocator current_allocator();
+hipError_t dev_alloc(const DevAllocator& a, void** p, size_t bytes, hipStream_t s);
+void dev_free(const DevAllocator& a, void* p, hipStream_t s);
+// before a custom allocator gets memory back: no enqueued work may still use
+// it (hipFree waits for the device by itself)
+void dev_release_begin(const DevAllocator& a);
+
 // One scan request.  geno points at the packed row of marker geno_row0
 // (0 for a caller's whole genotype matrix, the block's first marker for a
 // streamed block); rows [m0 - geno_row0, m1 - geno_row0) are read for the

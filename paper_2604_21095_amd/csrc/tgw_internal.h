@@ -20,10 +20,18 @@ constexpr int kBlockBytes8 = 6144;
 constexpr int kSlots = 32;      // correction slots per (marker, panel): dmu, Q^T g
 constexpr int kMaxCov = 31;     // K <= 31 so that q = K + 1 <= 32 slots
 constexpr int kMaxPanelsPerBind = 32;
-// A marker is degenerate when ||g_res||^2 <= kMarkerTol ||g_c||^2.  ||g_res||^2
-// is ||g_c||^2 - sum_k (q_k^T g)^2 with q_k^T g from the FP32-accumulated
-// contraction, which resolves the difference to about 1e-6 ||g_c||^2.
-constexpr double kMarkerTol = 1e-4;
+// Covariate-collinear markers.  The contraction's FP32 rounding error scales
+// with ||g_c|| while the statistic scales with ||g_res||, so the error in r
+// grows as (||g_res||^2 / ||g_c||^2)^-1/2.  A marker whose ||g_res||^2 (from
+// the FP32-accumulated Q^T g, good to about 1e-6 ||g_c||^2) is below
+// kRedoTol ||g_c||^2 is not finished by the main kernel (its rows there are
+// NaN) but by an FP64 kernel that residualizes it explicitly and contracts
+// it with the stored panel operand; that kernel calls it degenerate (NaN)
+// when its FP64 ||g_res||^2 <= kCollinearTol ||g_c||^2.
+constexpr double kRedoTol = 0.5;
+constexpr double kCollinearTol = 1e-8;
+constexpr int kRedoGroup = 16;   // listed markers per work item of the FP64 kernel
+constexpr int kRedoCols = 256;   // columns per work item (one per thread)
 
 // ---- p-value table ----------------------------------------------------------
 constexpr float kTMax = 40.0f;        // |t| beyond this goes to the FP64 tail
@@ -57,10 +65,12 @@ __host__ __device__ constexpr int hl_blocks(int q) { return q <= kHLSlots ? 1 : 
 // per-marker statistics of one marker block
 struct MarkerStat {
   double gc2;    // ||g_c||^2 of the mean-imputed marker (exact from integer counts)
-  float dmu;     // mu - c, c = mu rounded to 1/64 (BF16) or 1/512 (FP16 forms); 8-bit dosages: to an integer
+  float dmu;     // gs (mu - c): the operand value of a missing call before rounding
   int32_t flags; // 1 = degenerate (no observed call or monomorphic)
   double mu;
-  double shift;  // c
+  double shift;  // c: mu rounded to U / K (BF16), 1/512 (FP16 forms, FP32: 1/64); 8-bit dosages: to an integer
+  float gscale;  // gs: operand units per genotype unit of this marker (K / 128 for BF16, else 1)
+  int32_t pad;
 };
 
 struct PanelDev {
@@ -69,6 +79,8 @@ struct PanelDev {
   const float* cw;      // [P_pad][32]: (-sum_i y_op, -q_k^T y_op for k >= 1, 0 ...)
   const float4* table;  // per interval k: -log10 p(|t|) = c0 + c1 s + c2 s^2 + c3 s^3, s = 32|t| - k
   const uint8_t* lscale; // FP8 form: E8M0 scale of each column's lo term (NULL otherwise)
+  const double* Q;      // covariate basis, [q][n_pad] FP64 (the FP64 path of collinear markers)
+  const void* yop;      // operand base (column 0, chunk 0)
   int64_t n_pheno;
   float df;
   float sqrt_df;
@@ -148,7 +160,7 @@ struct GemmArgs {
   const uint4* mlut;     // [nm] decode table of each marker (2-bit codes, 16-bit forms: x lo bytes, y hi
                          // bytes, z FP8 bytes; FP32: the four values; 8-bit dosages: see kG8Lut)
   const float* wws;      // [nm][n_panels][32]
-  const float* invh;     // [nm][n_panels]
+  const float2* invh;    // [nm][n_panels]: 1 / (gs ||g_res||), 1 / ||g_res||
   float* raw_out;        // RAW mode destination
   int64_t raw_ld;
   TailDev tail;
@@ -166,6 +178,37 @@ struct StatsArgs {
   int32_t prec;        // Prec
   uint4* mlut;
   MarkerStat* mstat;
+  uint32_t* redo_count;  // [n_panels]: zeroed by the block's first workgroup
+  int32_t n_panels;
+};
+
+// markers left to the FP64 kernel, per panel: rows (within the marker block)
+// at entries[j * stride + k], k < count[j]
+struct RedoDev {
+  int32_t* entries;
+  uint32_t* count;
+  int64_t stride;
+};
+
+struct RedoArgs {
+  const uint8_t* geno;
+  int64_t row_bytes;
+  int64_t m0;        // row of the block's first marker in geno
+  int64_t n;         // samples
+  int64_t n_pad;
+  int32_t n_chunks;
+  int32_t code;      // tgw_geno_code
+  int32_t prec;
+  int32_t n_panels;
+  int32_t max_chunks;  // column chunks of kRedoCols in the widest panel
+  float gunit;
+  int64_t out_row0;
+  int64_t m_begin;
+  const MarkerStat* mstat;
+  const PanelDev* panels;
+  const OutDev* outs;
+  HitDev hits;
+  RedoDev redo;
 };
 
 struct BindArgs {
@@ -191,13 +234,15 @@ hipError_t launch_set_operand(const float* V, int64_t ldv, int64_t n, int64_t n_
                               void* yop, uint8_t* lscale, hipStream_t s);
 hipError_t launch_table(float4* table, double df, hipStream_t s);
 hipError_t launch_stats(const StatsArgs& a, hipStream_t s);
-hipError_t launch_finalize(const MarkerStat* ms, float* wws, float* invh, int64_t nm, int n_panels, float wscale,
-                           hipStream_t s);
+hipError_t launch_finalize(const MarkerStat* ms, float* wws, float2* invh, int64_t nm, int n_panels, float wscale,
+                           RedoDev redo, hipStream_t s);
+hipError_t launch_redo(const RedoArgs& a, int grid, hipStream_t s);
 hipError_t launch_bind(const BindArgs& a, hipStream_t s);
 hipError_t launch_tail_reset(TailDev t, hipStream_t s);
 hipError_t launch_tail(TailDev t, const PanelDev* panels, const OutDev* outs, HitDev hits, int64_t m_begin,
                        hipStream_t s);
-hipError_t launch_debug_stats(const MarkerStat* ms, int64_t nm, double* shift, double* mean, hipStream_t s);
+hipError_t launch_debug_stats(const MarkerStat* ms, int64_t nm, double* shift, double* mean, double* scale,
+                              hipStream_t s);
 
 // main contraction; `tile` selects one of the compiled tile shapes
 struct TileShape {

@@ -747,6 +747,8 @@ __device__ void stats_dosage8(const StatsArgs& a, int64_t m, int lane) {
   const double c = ok ? rint(mu) : 0.0;
   st.mu = mu;
   st.shift = c;
+  st.gscale = 1.0f;
+  st.pad = 0;
   st.gc2 = n_obs > 0 ? (double)num128 / (double)n_obs : 0.0;
   st.dmu = (float)(mu - c);
   const uint32_t nc = f16_bits_rn((float)(-1024.0 - c));
@@ -759,6 +761,8 @@ __device__ void stats_dosage8(const StatsArgs& a, int64_t m, int lane) {
 // per-marker statistics (one wave per marker)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void stats_kernel(StatsArgs a) {
+  if (blockIdx.x == 0 && a.redo_count)  // the FP64 list of this block starts empty
+    for (int j = threadIdx.x; j < a.n_panels; j += blockDim.x) a.redo_count[j] = 0u;
   const int lane = threadIdx.x & 63;
   const int64_t m = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (m >= a.nm) return;
@@ -801,30 +805,73 @@ __global__ __launch_bounds__(256) void stats_kernel(StatsArgs a) {
     c1 += __shfl_xor(c1, o);
     c2 += __shfl_xor(c2, o);
   }
-  if (lane != 0) return;
   const int64_t n_obs = a.n - nmiss;
   const int64_t sg = c1 + 2 * (int64_t)c2;
   const int64_t sg2 = c1 + 4 * (int64_t)c2;
   const int64_t num = n_obs * sg2 - sg * sg;  // n_obs * sum (g - mu)^2
   const bool ok = n_obs > 0 && num != 0;
+  const double mu = n_obs > 0 ? (double)sg / (double)n_obs : 0.0;
+  // operand value of a call g: gs (g - c); of a missing call: gs (mu - c)
+  // rounded to the operand type.  FP16 forms: gs = 1, c on the 1/512 grid
+  // (g - c exact in 11 bits, missing value to 2^-21).  FP32: gs = 1, c on
+  // the 1/64 grid.  BF16 (8 significant bits): gs = K / 128 and c = U / K
+  // with integers K >= 1 and U = rint(K mu) such that the calls' values
+  // (-U, K - U, 2K - U) / 128 have magnitude <= 2, hence are exact; of those
+  // K, the one whose missing value (K mu - U) / 128 rounds to BF16 with the
+  // smallest error per genotype unit (ties: the larger K).  The error is
+  // about 2^-9 |mu - U / K|: at most about 2^-18 (mu within 1/512 of a
+  // simple fraction such as 1/2 or 1), typically below 2^-24, against up
+  // to 2^-16 for the nearest multiple of 1/64.  The 256 candidates are
+  // spread over the wave's lanes.
+  double c = 0.0, gs = 1.0, vmiss = mu, vg[3] = {0.0, 1.0, 2.0};  // degenerate: not re-centred
+  if (ok && a.prec == kSplit) {
+    double best = INFINITY;
+    int bk = 0;
+    for (int K = 256 - lane; K >= 1; K -= 64) {
+      const double km = (double)K * mu;
+      const double U = rint(km);
+      if (U > 256.0 || 2.0 * K - U > 256.0) continue;
+      const double v = (km - U) * (1.0 / 128.0);
+      const double err = fabs((double)bf16_to_float(bf16_bits_rne((float)v)) - v) / (double)K;
+      if (err < best) {  // K descends: ties keep the larger K
+        best = err;
+        bk = K;
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ob = __shfl_xor(best, o);
+      const int ok2 = __shfl_xor(bk, o);
+      if (ob < best || (ob == best && ok2 > bk)) {
+        best = ob;
+        bk = ok2;
+      }
+    }
+    const double Kd = (double)bk, U = rint(Kd * mu);
+    gs = Kd / 128.0;
+    c = U / Kd;
+    vmiss = (Kd * mu - U) * (1.0 / 128.0);
+    for (int g = 0; g < 3; ++g) vg[g] = ((double)g * Kd - U) * (1.0 / 128.0);
+  } else if (ok) {
+    const double grid = f16_scaled(a.prec) ? 512.0 : 64.0;
+    c = rint(grid * mu) / grid;
+    vmiss = mu - c;
+    for (int g = 0; g < 3; ++g) vg[g] = (double)g - c;
+  }
+  if (lane != 0) return;
   MarkerStat st;
   st.flags = ok ? 0 : 1;
-  const double mu = n_obs > 0 ? (double)sg / (double)n_obs : 0.0;
-  // re-centring grid: 1/64 keeps g - c exact in BF16 (8 significant bits),
-  // 1/512 in FP16 (11 bits)
-  const double grid = f16_scaled(a.prec) ? 512.0 : 64.0;
-  const double c = ok ? rint(grid * mu) / grid : 0.0;
   st.mu = mu;
   st.shift = c;
+  st.gscale = (float)gs;
+  st.pad = 0;
   st.gc2 = n_obs > 0 ? (double)num / (double)n_obs : 0.0;
-  st.dmu = (float)(mu - c);
+  st.dmu = (float)vmiss;
   // operand value of each 2-bit code, in the coding scheme's code order
   double val[4];
-  const double vmiss = mu - c;
   if (a.code == 0) {
-    val[0] = 0.0 - c; val[1] = 1.0 - c; val[2] = 2.0 - c; val[3] = vmiss;
+    val[0] = vg[0]; val[1] = vg[1]; val[2] = vg[2]; val[3] = vmiss;
   } else {
-    val[0] = 0.0 - c; val[1] = vmiss; val[2] = 1.0 - c; val[3] = 2.0 - c;
+    val[0] = vg[0]; val[1] = vmiss; val[2] = vg[1]; val[3] = vg[2];
   }
   uint4 lut;
   if (a.prec != kFP32) {
@@ -844,32 +891,45 @@ __global__ __launch_bounds__(256) void stats_kernel(StatsArgs a) {
   a.mstat[m] = st;
 }
 
-__global__ void debug_stats_kernel(const MarkerStat* ms, int64_t nm, double* shift, double* mean) {
+__global__ void debug_stats_kernel(const MarkerStat* ms, int64_t nm, double* shift, double* mean, double* scale) {
   const int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (m >= nm) return;
   if (shift) shift[m] = ms[m].shift;
   if (mean) mean[m] = ms[m].mu;
+  if (scale) scale[m] = (double)ms[m].gscale;
 }
 
 // ---------------------------------------------------------------------------
 // ||g_res||^2 per (marker, panel) from Q^T g; slot 0 <- mu - c
 // ---------------------------------------------------------------------------
+// The slots and the contraction are in operand units (gs per genotype unit),
+// so r takes 1 / (gs ||g_res||) and beta, SE take 1 / ||g_res||.  Markers
+// whose ||g_res||^2 here is below kRedoTol ||g_c||^2 get NaN (the main
+// kernel then writes NaN rows and no reduced outputs) and go to the FP64
+// list of their panel.
 __global__ void finalize_kernel(const MarkerStat* __restrict__ ms, float* __restrict__ wws,
-                                float* __restrict__ invh, int64_t nm, int n_panels, float wscale) {
+                                float2* __restrict__ invh, int64_t nm, int n_panels, float wscale, RedoDev redo) {
   const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (idx >= nm * n_panels) return;
   const int64_t m = idx / n_panels;
   const MarkerStat st = ms[m];
   float* ws = wws + idx * kSlots;
+  const double igs = 1.0 / (double)st.gscale;  // exact: gs is K / 128 or 1
   double h2 = st.gc2;
   for (int k = 1; k < kSlots; ++k) {
     const float wf = ws[k] * wscale;  // undo the operand scale of the Q columns
     ws[k] = wf;
-    const double w = (double)wf;
+    const double w = (double)wf * igs;
     h2 -= w * w;
   }
-  const bool ok = st.flags == 0 && h2 > kMarkerTol * st.gc2;
-  invh[idx] = ok ? (float)(1.0 / sqrt(h2)) : __builtin_nanf("");
+  const bool ok = st.flags == 0 && h2 > kRedoTol * st.gc2;
+  if (st.flags == 0 && !ok) {
+    const int j = (int)(idx - m * n_panels);
+    const uint32_t k = atomicAdd(redo.count + j, 1u);
+    redo.entries[j * redo.stride + k] = (int32_t)m;  // at most one entry per (marker, panel): never full
+  }
+  const double ih = 1.0 / sqrt(h2);
+  invh[idx] = ok ? make_float2((float)(ih * igs), (float)ih) : make_float2(__builtin_nanf(""), __builtin_nanf(""));
   ws[0] = st.dmu;
 }
 
@@ -921,6 +981,183 @@ __global__ void tail_kernel(TailDev t, const PanelDev* __restrict__ panels, cons
     if (o.nl) o.nl[e.row * o.ld + e.col] = nl;
     if (o.best) atomicMax(o.best + e.col, best_pack(nl, m_begin + e.row));  // replaces the lower bound
     if (hits.entries && nl >= hits.threshold) append_hit(hits, m_begin + e.row, e.panel, e.col, nl, e.r);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 path of covariate-collinear markers (the ones finalize_kernel lists):
+// each listed marker is mean-imputed and residualized explicitly against its
+// panel's FP64 Q, g_res = g_imp - Q (Q^T g_imp), then contracted in FP64 with
+// the stored panel operand, so that r = g_res^T y_op / (||g_res|| ||(I -
+// QQ^T) y_op||) carries no cancellation; t, beta, SE as in the main epilogue
+// (Eq. 3), -log10 p in FP64 for every test, and the reduced outputs.  A
+// marker with ||g_res||^2 <= kCollinearTol ||g_c||^2 gives NaN rows.  One
+// work item: up to kRedoGroup listed markers of one panel x kRedoCols of its
+// columns (one per thread), walked by a persistent grid; the work list comes
+// from the per-panel counts, so a block without listed markers costs one
+// short launch.
+// ---------------------------------------------------------------------------
+constexpr int kRedoThreads = kRedoCols;
+static_assert(kRedoGroup % (kRedoThreads / 64) == 0 && kRedoGroup * kChunk == 4 * kRedoThreads, "redo shape");
+
+// the operand value stored for (column, sample), in the units the main kernel
+// contracts (2^12 y~ for the FP16 forms), i.e. what prep_kernel accumulated
+// into the column's norm and projections
+__device__ inline double load_operand(const void* op, int prec, int64_t col, int64_t i, int n_chunks, int lsh) {
+  if (prec == kSplit8) {
+    const uint32_t hb = ((const uint16_t*)op)[operand_index_split(col, i, n_chunks, 0, kBlockBytes8 / 2)];
+    const uint32_t qb = ((const uint8_t*)op)[operand_index_lo8(col, i, n_chunks)];
+    return (double)f16_to_float(hb) + ldexp(e4m3_value(qb), -lsh);
+  }
+  if (prec == kSplit16 || prec == kSplit) {
+    const uint16_t* p = (const uint16_t*)op;
+    const uint32_t hb = p[operand_index_split(col, i, n_chunks, 0)];
+    const uint32_t lb = p[operand_index_split(col, i, n_chunks, 1)];
+    return prec == kSplit16 ? (double)f16_to_float(hb) + (double)f16_to_float(lb)
+                            : (double)bf16_to_float(hb) + (double)bf16_to_float(lb);
+  }
+  return (double)((const float*)op)[operand_index_fp32(col, i, n_chunks)];
+}
+
+// sample i of a genotype row in genotype units (8-bit dosages: q), NaN if missing
+__device__ inline double geno_value(const uint8_t* row, int code, int64_t i) {
+  if (code == 2) {  // 8-bit dosages
+    const uint32_t q = row[i];
+    return q == 255u ? __builtin_nan("") : (double)q;
+  }
+  const uint32_t v = (row[i >> 2] >> (2 * (i & 3))) & 3u;
+  if (code == 0) return v == 3u ? __builtin_nan("") : (double)v;
+  return v == 1u ? __builtin_nan("") : (v == 0u ? 0.0 : (double)(v - 1u));  // PLINK .bed order
+}
+
+__global__ __launch_bounds__(kRedoThreads) void redo_kernel(RedoArgs a) {
+  constexpr int NW = kRedoThreads / 64;
+  constexpr int PPT = kRedoGroup / NW;  // (marker, sample) pairs per thread in a chunk
+  __shared__ double w_s[kRedoGroup][kSlots];
+  __shared__ double gr_s[kRedoGroup][kChunk];
+  __shared__ double h2_s[kRedoGroup];
+  __shared__ double sh[NW * kSlots];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  int64_t total = 0;
+  for (int j = 0; j < a.n_panels; ++j)
+    total += (int64_t)((a.redo.count[j] + kRedoGroup - 1) / kRedoGroup) * a.max_chunks;
+  for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
+    int64_t rem = w;
+    int j = 0;
+    uint32_t cnt = 0;
+    for (; j < a.n_panels; ++j) {
+      cnt = a.redo.count[j];
+      const int64_t items = (int64_t)((cnt + kRedoGroup - 1) / kRedoGroup) * a.max_chunks;
+      if (rem < items) break;
+      rem -= items;
+    }
+    const int gi = (int)(rem / a.max_chunks);
+    const int cc = (int)(rem - (int64_t)gi * a.max_chunks);
+    const PanelDev pd = a.panels[j];
+    if ((int64_t)cc * kRedoCols >= pd.n_pheno) continue;  // uniform over the workgroup
+    const int ng = min(kRedoGroup, (int)cnt - gi * kRedoGroup);
+    const int32_t* ent = a.redo.entries + j * a.redo.stride + (int64_t)gi * kRedoGroup;
+    const int q = pd.q;
+    // w = Q^T g_imp of each listed marker
+    for (int e = 0; e < ng; ++e) {
+      const int64_t m = ent[e];
+      const double mu = a.mstat[m].mu;
+      const uint8_t* row = a.geno + (a.m0 + m) * a.row_bytes;
+      double acc[kSlots];
+#pragma unroll
+      for (int k = 0; k < kSlots; ++k) acc[k] = 0.0;
+      for (int64_t i = tid; i < a.n; i += kRedoThreads) {
+        double g = geno_value(row, a.code, i);
+        if (g != g) g = mu;
+#pragma unroll
+        for (int k = 0; k < kSlots; ++k)
+          if (k < q) acc[k] += pd.Q[(int64_t)k * a.n_pad + i] * g;
+      }
+      block_sum_vec<kRedoThreads, kSlots>(acc, sh);
+#pragma unroll
+      for (int k = 0; k < kSlots; ++k)
+        if (tid == k) w_s[e][k] = acc[k];
+    }
+    // chunks of 64 samples: residualized genotypes into LDS, then each thread
+    // contracts them with its column of the operand
+    const int64_t p = (int64_t)cc * kRedoCols + tid;
+    const bool colok = p < pd.n_pheno;
+    const int lsh = (a.prec == kSplit8 && colok) ? 127 - (int)pd.lscale[p] : 0;
+    double S[kRedoGroup], h2r[PPT];
+#pragma unroll
+    for (int e = 0; e < kRedoGroup; ++e) S[e] = 0.0;
+#pragma unroll
+    for (int r = 0; r < PPT; ++r) h2r[r] = 0.0;
+    for (int ch = 0; ch < a.n_chunks; ++ch) {
+      __syncthreads();  // w_s written; the previous chunk's gr_s read
+#pragma unroll
+      for (int r = 0; r < PPT; ++r) {
+        const int e = wave + NW * r;
+        const int64_t i = (int64_t)ch * kChunk + lane;
+        double v = 0.0;
+        if (e < ng && i < a.n) {
+          const int64_t m = ent[e];
+          double g = geno_value(a.geno + (a.m0 + m) * a.row_bytes, a.code, i);
+          if (g != g) g = a.mstat[m].mu;
+          v = g;
+          for (int k = 0; k < q; ++k) v -= pd.Q[(int64_t)k * a.n_pad + i] * w_s[e][k];
+          h2r[r] += v * v;
+        }
+        gr_s[e][lane] = v;
+      }
+      __syncthreads();
+      if (colok) {
+        const int ns = (int)min((int64_t)kChunk, a.n - (int64_t)ch * kChunk);
+        for (int s = 0; s < ns; ++s) {
+          const double y = load_operand(pd.yop, a.prec, p, (int64_t)ch * kChunk + s, a.n_chunks, lsh);
+#pragma unroll
+          for (int e = 0; e < kRedoGroup; ++e) S[e] += gr_s[e][s] * y;
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < PPT; ++r) {
+      double v = h2r[r];
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+      if (lane == 0) h2_s[wave + NW * r] = v;
+    }
+    __syncthreads();
+    if (colok) {
+      const double invny = (double)pd.invny[p];
+      const double sp = (double)pd.scale[p] * (double)a.gunit;
+      const double df = (double)pd.df;
+      const OutDev od = a.outs[j];
+#pragma unroll
+      for (int e = 0; e < kRedoGroup; ++e) {
+        if (e >= ng) break;
+        const int64_t m = ent[e];
+        const int64_t row = a.out_row0 + m;
+        const double h2 = h2_s[e];
+        const bool ok = h2 > kCollinearTol * a.mstat[m].gc2 && invny == invny;
+        double r = __builtin_nan(""), t = r, beta = r, se = r, nl = r;
+        if (ok) {
+          const double ih = 1.0 / sqrt(h2);
+          r = S[e] * invny * ih;
+          r = r > 1.0 ? 1.0 : (r < -1.0 ? -1.0 : r);
+          const double omr2 = (1.0 - r) * (1.0 + r);
+          t = omr2 > 0.0 ? r * sqrt(df / omr2) : (r > 0.0 ? INFINITY : -INFINITY);
+          beta = r * sp * ih;
+          se = sp * ih * sqrt(omr2 / df);
+          nl = -ln_p_two_sided(t, df) / M_LN10;
+        }
+        const int64_t o = row * od.ld + p;
+        if (od.r) od.r[o] = (float)r;
+        if (od.beta) od.beta[o] = (float)beta;
+        if (od.se) od.se[o] = (float)se;
+        if (od.t) od.t[o] = (float)t;
+        if (od.nl) od.nl[o] = (float)nl;
+        if (ok && od.best) atomicMax(od.best + p, best_pack((float)nl, a.m_begin + row));
+        if (ok && a.hits.entries && (float)nl >= a.hits.threshold)
+          append_hit(a.hits, a.m_begin + row, j, p, (float)nl, (float)r);
+      }
+    }
+    __syncthreads();  // h2_s and w_s are rewritten by the next work item
   }
 }
 
@@ -1032,7 +1269,8 @@ __device__ __forceinline__ void epilogue_rare(bool to_tail, float nl, float at, 
 // loads inside the row loop would serialise behind the previous row's stores).
 struct GlobalRows {};
 __device__ __forceinline__ float* at_byte(float* base, uint32_t ob) { return (float*)((char*)base + ob); }
-typedef const __attribute__((address_space(3))) float* LdsRows;
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef const __attribute__((address_space(3))) f32x2* LdsRows;
 
 template <int WMF, class TabPtr, class IhPtr>
 __device__ __forceinline__ void finish_block(const float* stage, const GemmArgs& a, const ColBlock& blk,
@@ -1092,7 +1330,8 @@ __device__ __forceinline__ void finish_block(const float* stage, const GemmArgs&
   constexpr int R = 4;
   static_assert((WMF * 16) % R == 0, "row groups");
   for (int g = 0; g < WMF * 16; g += R) {
-    float Sv[R], ihv[R];
+    float Sv[R];
+    f32x2 ihv[R];  // 1 / (gs ||g_res||) for r, 1 / ||g_res|| for beta and SE
 #pragma unroll
     for (int i = 0; i < R; ++i) {
       const int rr = h + 2 * (g + i);
@@ -1100,7 +1339,8 @@ __device__ __forceinline__ void finish_block(const float* stage, const GemmArgs&
       if constexpr (std::is_same<IhPtr, GlobalRows>::value) {
         int64_t mr = rowbase + rr;
         mr = mr < a.nm ? mr : a.nm - 1;
-        ihv[i] = gload<float>(a.invh + mr * a.n_panels + j);
+        const float2 v = gload<float2>(a.invh + mr * a.n_panels + j);
+        ihv[i] = f32x2{v.x, v.y};
       } else {
         ihv[i] = ih[rr];
       }
@@ -1111,8 +1351,8 @@ __device__ __forceinline__ void finish_block(const float* stage, const GemmArgs&
     for (int i = 0; i < R; ++i) {
       const int rr = h + 2 * (g + i);
       okv[i] = colok && rowbase + rr < a.nm;
-      const float invh = ihv[i];
-      float r = Sv[i] * invh * invny;
+      const float invh = ihv[i].y;
+      float r = Sv[i] * ihv[i].x * invny;
       if (r > 1.0f) r = 1.0f;
       if (r < -1.0f) r = -1.0f;
       // 1 - r^2 is 0 or at least about 2^-24, never subnormal: the hardware
@@ -1634,7 +1874,7 @@ __global__ __launch_bounds__(NW * 64) void gemm_wide_kernel(GemmArgs a) {
   // past the stages: each row's 1/||g_res|| of the current column panel and,
   // where it fits, that panel's p-value table; the epilogue then reads
   // nothing from global memory between its output stores
-  constexpr int IH_BYTES = TM * 4;
+  constexpr int IH_BYTES = TM * 8;
   constexpr int TAB_BYTES = kTabIntervals * 16;
   constexpr bool LT = LDS_BYTES + IH_BYTES + TAB_BYTES <= 160 * 1024;
   static_assert(WMF % 2 == 0 && LDS_BYTES + IH_BYTES <= 160 * 1024, "epilogue rows in LDS");
@@ -2119,13 +2359,13 @@ __global__ __launch_bounds__(NW * 64) void gemm_wide_kernel(GemmArgs a) {
         csp[fn] = colok ? gload<float>(pdb.scale + blk.col0 + r32) * a.gunit : 0.f;
       }
       // the wave's rows' 1/||g_res|| for panel j, one or two rows per lane
-      float* ihl = (float*)(smem + LDS_BYTES) + __builtin_amdgcn_readfirstlane(wave) * (WMF * 32);
+      float2* ihl = (float2*)(smem + LDS_BYTES) + __builtin_amdgcn_readfirstlane(wave) * (WMF * 32);
       auto load_rows = [&](int j) {
 #pragma unroll
         for (int k = 0; k < WMF / 2; ++k) {
           int64_t mr = rowbase + 64 * k + lane;
           mr = mr < a.nm ? mr : a.nm - 1;
-          ihl[64 * k + lane] = gload<float>(a.invh + mr * a.n_panels + j);
+          ihl[64 * k + lane] = gload<float2>(a.invh + mr * a.n_panels + j);
         }
       };
       // panel j's table into LDS (all threads; the caller brackets it with barriers)
@@ -2438,11 +2678,17 @@ hipError_t launch_stats(const StatsArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(const MarkerStat* ms, float* wws, float* invh, int64_t nm, int n_panels, float wscale,
+hipError_t launch_finalize(const MarkerStat* ms, float* wws, float2* invh, int64_t nm, int n_panels, float wscale,
+                           RedoDev redo,
                            hipStream_t s) {
   const int64_t total = nm * n_panels;
   hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, ms, wws, invh, nm,
-                     n_panels, wscale);
+                     n_panels, wscale, redo);
+  return hipGetLastError();
+}
+
+hipError_t launch_redo(const RedoArgs& a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(redo_kernel, dim3((unsigned)grid), dim3(kRedoThreads), 0, s, a);
   return hipGetLastError();
 }
 
@@ -2462,8 +2708,10 @@ hipError_t launch_tail(TailDev t, const PanelDev* panels, const OutDev* outs, Hi
   return hipGetLastError();
 }
 
-hipError_t launch_debug_stats(const MarkerStat* ms, int64_t nm, double* shift, double* mean, hipStream_t s) {
-  hipLaunchKernelGGL(debug_stats_kernel, dim3((unsigned)((nm + 255) / 256)), dim3(256), 0, s, ms, nm, shift, mean);
+hipError_t launch_debug_stats(const MarkerStat* ms, int64_t nm, double* shift, double* mean, double* scale,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(debug_stats_kernel, dim3((unsigned)((nm + 255) / 256)), dim3(256), 0, s, ms, nm, shift, mean,
+                     scale);
   return hipGetLastError();
 }
 

@@ -67,17 +67,77 @@ static tgw_status device_info(int* dev_out, DevInfo* info) {
 
 static int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
-template <class T>
-static hipError_t dmalloc(T** p, size_t count) {
+// ---------------------------------------------------------------------------
+// device memory
+// ---------------------------------------------------------------------------
+static std::mutex g_alloc_mu;
+static DevAllocator g_alloc;
+
+DevAllocator tgw::current_allocator() {
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  return g_alloc;
+}
+
+hipError_t tgw::dev_alloc(const DevAllocator& a, void** p, size_t bytes, hipStream_t s) {
   *p = nullptr;
-  if (count == 0) count = 1;
-  return hipMalloc((void**)p, count * sizeof(T));
+  if (bytes == 0) bytes = 1;
+  if (!a.alloc) return hipMalloc(p, bytes);
+  *p = a.alloc(bytes, (void*)s, a.ctx);
+  return *p ? hipSuccess : hipErrorOutOfMemory;
+}
+
+void tgw::dev_free(const DevAllocator& a, void* p, hipStream_t s) {
+  if (!p) return;
+  if (!a.free) {
+    (void)hipFree(p);
+    return;
+  }
+  a.free(p, (void*)s, a.ctx);
+}
+
+void tgw::dev_release_begin(const DevAllocator& a) {
+  if (a.free) (void)hipDeviceSynchronize();
+}
+
+extern "C" tgw_status tgw_set_allocator(tgw_alloc_fn alloc_fn, tgw_free_fn free_fn, void* ctx) {
+  if ((alloc_fn == nullptr) != (free_fn == nullptr))
+    return fail(TGW_ERR_INVALID_ARG, "give both allocator functions or neither");
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  g_alloc.alloc = alloc_fn;
+  g_alloc.free = free_fn;
+  g_alloc.ctx = alloc_fn ? ctx : nullptr;
+  return TGW_OK;
+}
+
+extern "C" void* tgw_debug_counting_alloc(size_t bytes, void* stream, void* ctx) {
+  (void)stream;
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+  auto* c = (tgw_debug_alloc_counts*)ctx;
+  __atomic_add_fetch(&c->n_alloc, 1, __ATOMIC_RELAXED);
+  __atomic_add_fetch(&c->bytes, (int64_t)bytes, __ATOMIC_RELAXED);
+  return p;
+}
+
+extern "C" void tgw_debug_counting_free(void* ptr, void* stream, void* ctx) {
+  (void)stream;
+  (void)hipFree(ptr);
+  __atomic_add_fetch(&((tgw_debug_alloc_counts*)ctx)->n_free, 1, __ATOMIC_RELAXED);
+}
+
+template <class T>
+static hipError_t dmalloc(const DevAllocator& a, T** p, size_t count, hipStream_t s = nullptr) {
+  void* v = nullptr;
+  const hipError_t e = dev_alloc(a, &v, (count ? count : 1) * sizeof(T), s);
+  *p = (T*)v;
+  return e;
 }
 
 // ---------------------------------------------------------------------------
 // handles
 // ---------------------------------------------------------------------------
 struct tgw_covariates {
+  DevAllocator mem;
   int device = 0;
   int64_t n = 0, n_pad = 0;
   int q = 0, n_chunks = 0;
@@ -88,6 +148,7 @@ struct tgw_covariates {
 };
 
 struct tgw_panel {
+  DevAllocator mem;
   const tgw_covariates* cov = nullptr;
   int64_t P = 0, P_pad = 0;
   int prec = 0;
@@ -101,6 +162,7 @@ struct tgw_panel {
 };
 
 struct tgw_plan {
+  DevAllocator mem;
   std::vector<const tgw_panel*> panels;
   int device = 0, prec = 0, n_cu = 0;
   std::string arch;
@@ -114,7 +176,10 @@ struct tgw_plan {
   uint4* mlut = nullptr;
   MarkerStat* mstat = nullptr;
   float* wws = nullptr;
-  float* invh = nullptr;
+  float2* invh = nullptr;
+  int32_t* redo_entries = nullptr;  // FP64 list of covariate-collinear markers: [n_panels][MB]
+  uint32_t* redo_count = nullptr;   // [n_panels]
+  int max_chunks = 0;               // kRedoCols-column chunks of the widest panel
   TailEntry* tail_entries = nullptr;
   unsigned long long* tail_count = nullptr;
   int64_t tail_cap = 0;
@@ -178,9 +243,10 @@ extern "C" tgw_status tgw_tile_shape(int32_t idx, int32_t* tile_markers, int32_t
 // ---------------------------------------------------------------------------
 extern "C" void tgw_covariates_free(tgw_covariates* cov) {
   if (!cov) return;
-  (void)hipFree(cov->Q);
-  (void)hipFree(cov->wop_fp32);
-  for (int k = 0; k < kNumPrec; ++k) (void)hipFree(cov->wop_hl[k]);
+  dev_release_begin(cov->mem);
+  dev_free(cov->mem, cov->Q, nullptr);
+  dev_free(cov->mem, cov->wop_fp32, nullptr);
+  for (int k = 0; k < kNumPrec; ++k) dev_free(cov->mem, cov->wop_hl[k], nullptr);
   delete cov;
 }
 
@@ -198,6 +264,7 @@ extern "C" tgw_status tgw_fit_covariates(int64_t n_samples, int32_t n_cov, const
   if (st != TGW_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   auto* cov = new tgw_covariates();
+  cov->mem = current_allocator();
   cov->device = dev;
   cov->n = n_samples;
   cov->n_pad = round_up(n_samples, kChunk);
@@ -205,20 +272,21 @@ extern "C" tgw_status tgw_fit_covariates(int64_t n_samples, int32_t n_cov, const
   cov->n_chunks = (int)(cov->n_pad / kChunk);
   double *X = nullptr, *rdiag = nullptr, *qrs = nullptr;
   int32_t* flags = nullptr;
-  auto cleanup = [&]() {
-    (void)hipFree(X);
-    (void)hipFree(rdiag);
-    (void)hipFree(qrs);
-    (void)hipFree(flags);
+  const DevAllocator& A = cov->mem;
+  auto cleanup = [&]() {  // after the stream has been synchronized
+    dev_free(A, X, s);
+    dev_free(A, rdiag, s);
+    dev_free(A, qrs, s);
+    dev_free(A, flags, s);
   };
-  hipError_t e = dmalloc(&cov->Q, (size_t)cov->q * cov->n_pad);
-  if (e == hipSuccess) e = dmalloc(&X, (size_t)cov->q * cov->n_pad);
-  if (e == hipSuccess) e = dmalloc(&rdiag, (size_t)cov->q);
-  if (e == hipSuccess) e = dmalloc(&qrs, (size_t)kQrScratch);
-  if (e == hipSuccess) e = dmalloc(&flags, 2);
-  if (e == hipSuccess) e = hipMalloc(&cov->wop_fp32, (size_t)cov->n_chunks * kBlockBytes);
+  hipError_t e = dmalloc(A, &cov->Q, (size_t)cov->q * cov->n_pad, s);
+  if (e == hipSuccess) e = dmalloc(A, &X, (size_t)cov->q * cov->n_pad, s);
+  if (e == hipSuccess) e = dmalloc(A, &rdiag, (size_t)cov->q, s);
+  if (e == hipSuccess) e = dmalloc(A, &qrs, (size_t)kQrScratch, s);
+  if (e == hipSuccess) e = dmalloc(A, &flags, 2, s);
+  if (e == hipSuccess) e = dev_alloc(A, &cov->wop_fp32, (size_t)cov->n_chunks * kBlockBytes, s);
   for (int k : {(int)kSplit, (int)kSplit16})
-    if (e == hipSuccess) e = hipMalloc(&cov->wop_hl[k], (size_t)hl_blocks(cov->q) * cov->n_chunks * kBlockBytes);
+    if (e == hipSuccess) e = dev_alloc(A, &cov->wop_hl[k], (size_t)hl_blocks(cov->q) * cov->n_chunks * kBlockBytes, s);
   if (e == hipSuccess) e = hipMemsetAsync(flags, 0, 2 * sizeof(int32_t), s);
   if (e == hipSuccess) e = launch_qr(d_C, ldc, n_samples, cov->n_pad, cov->q, X, cov->Q, rdiag, qrs, flags, s);
   if (e == hipSuccess)
@@ -226,6 +294,7 @@ extern "C" tgw_status tgw_fit_covariates(int64_t n_samples, int32_t n_cov, const
   int32_t hf[2] = {0, 0};
   if (e == hipSuccess) e = hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) (void)hipStreamSynchronize(s);  // nothing enqueued may still use the temporaries
   cleanup();
   if (e != hipSuccess) {
     tgw_covariates_free(cov);
@@ -259,12 +328,13 @@ extern "C" tgw_status tgw_covariates_q(const tgw_covariates* cov, double* d_Q, i
 // ---------------------------------------------------------------------------
 extern "C" void tgw_panel_free(tgw_panel* p) {
   if (!p) return;
-  (void)hipFree(p->yop);
-  (void)hipFree(p->scale);
-  (void)hipFree(p->invny);
-  (void)hipFree(p->cw);
-  (void)hipFree(p->table);
-  (void)hipFree(p->lscale);
+  dev_release_begin(p->mem);
+  dev_free(p->mem, p->yop, nullptr);
+  dev_free(p->mem, p->scale, nullptr);
+  dev_free(p->mem, p->invny, nullptr);
+  dev_free(p->mem, p->cw, nullptr);
+  dev_free(p->mem, p->table, nullptr);
+  dev_free(p->mem, p->lscale, nullptr);
   delete p;
 }
 
@@ -286,6 +356,7 @@ extern "C" tgw_status tgw_prepare_phenotypes(const tgw_covariates* cov, int64_t 
   if (dev != cov->device) return fail(TGW_ERR_INVALID_ARG, "covariates live on another device");
   hipStream_t s = (hipStream_t)stream;
   auto* p = new tgw_panel();
+  p->mem = current_allocator();
   p->cov = cov;
   p->P = n_pheno;
   p->P_pad = round_up(n_pheno, kColBlock);
@@ -296,14 +367,15 @@ extern "C" tgw_status tgw_prepare_phenotypes(const tgw_covariates* cov, int64_t 
   p->df = cov->n - cov->q - 1;
   int32_t* flags = nullptr;
   const size_t op_bytes = (size_t)(p->P_pad / kColBlock) * cov->n_chunks * block_bytes(p->prec);
-  hipError_t e = hipMalloc(&p->yop, op_bytes);
-  if (e == hipSuccess) e = dmalloc(&p->lscale, p->P_pad);
+  const DevAllocator& A = p->mem;
+  hipError_t e = dev_alloc(A, &p->yop, op_bytes, s);
+  if (e == hipSuccess) e = dmalloc(A, &p->lscale, p->P_pad, s);
   if (e == hipSuccess) e = hipMemsetAsync(p->lscale, 127, p->P_pad, s);
-  if (e == hipSuccess) e = dmalloc(&p->scale, p->P_pad);
-  if (e == hipSuccess) e = dmalloc(&p->invny, p->P_pad);
-  if (e == hipSuccess) e = dmalloc(&p->cw, (size_t)p->P_pad * kSlots);
-  if (e == hipSuccess) e = dmalloc(&p->table, kTabIntervals);
-  if (e == hipSuccess) e = dmalloc(&flags, 1);
+  if (e == hipSuccess) e = dmalloc(A, &p->scale, p->P_pad, s);
+  if (e == hipSuccess) e = dmalloc(A, &p->invny, p->P_pad, s);
+  if (e == hipSuccess) e = dmalloc(A, &p->cw, (size_t)p->P_pad * kSlots, s);
+  if (e == hipSuccess) e = dmalloc(A, &p->table, kTabIntervals, s);
+  if (e == hipSuccess) e = dmalloc(A, &flags, 1, s);
   if (e == hipSuccess) e = hipMemsetAsync(p->yop, 0, op_bytes, s);
   if (e == hipSuccess) e = hipMemsetAsync(p->scale, 0, p->P_pad * sizeof(float), s);
   if (e == hipSuccess) e = hipMemsetAsync(p->invny, 0, p->P_pad * sizeof(float), s);
@@ -316,7 +388,8 @@ extern "C" tgw_status tgw_prepare_phenotypes(const tgw_covariates* cov, int64_t 
   int32_t hf = 0;
   if (e == hipSuccess) e = hipMemcpyAsync(&hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  (void)hipFree(flags);
+  if (e != hipSuccess) (void)hipStreamSynchronize(s);  // nothing enqueued may still use flags
+  dev_free(A, flags, s);
   if (e != hipSuccess) {
     tgw_panel_free(p);
     return hip_fail(e, "tgw_prepare_phenotypes");
@@ -358,16 +431,20 @@ extern "C" void tgw_plan_free(tgw_plan* pl) {
     (void)hipEventDestroy(ev.first);
     (void)hipEventDestroy(ev.second);
   }
-  (void)hipFree(pl->d_cb_main);
-  (void)hipFree(pl->d_cb_w);
-  (void)hipFree(pl->d_panels);
-  (void)hipFree(pl->d_outs);
-  (void)hipFree(pl->mlut);
-  (void)hipFree(pl->mstat);
-  (void)hipFree(pl->wws);
-  (void)hipFree(pl->invh);
-  (void)hipFree(pl->tail_entries);
-  (void)hipFree(pl->tail_count);
+  const DevAllocator& A = pl->mem;
+  dev_release_begin(A);
+  dev_free(A, pl->d_cb_main, nullptr);
+  dev_free(A, pl->d_cb_w, nullptr);
+  dev_free(A, pl->d_panels, nullptr);
+  dev_free(A, pl->d_outs, nullptr);
+  dev_free(A, pl->mlut, nullptr);
+  dev_free(A, pl->mstat, nullptr);
+  dev_free(A, pl->wws, nullptr);
+  dev_free(A, pl->invh, nullptr);
+  dev_free(A, pl->redo_entries, nullptr);
+  dev_free(A, pl->redo_count, nullptr);
+  dev_free(A, pl->tail_entries, nullptr);
+  dev_free(A, pl->tail_count, nullptr);
   delete pl;
 }
 
@@ -451,6 +528,7 @@ extern "C" tgw_status tgw_plan_create(const tgw_panel* const* panels, int32_t n_
   if (o.tile >= n_tile_shapes()) return fail(TGW_ERR_INVALID_ARG, "tile index out of range");
 
   auto* pl = new tgw_plan();
+  pl->mem = current_allocator();
   pl->panels.assign(panels, panels + n_panels);
   pl->device = dev;
   pl->n_cu = info.n_cu;
@@ -498,6 +576,9 @@ extern "C" tgw_status tgw_plan_create(const tgw_panel* const* panels, int32_t n_
     d.scale = p->scale;
     d.invny = p->invny;
     d.cw = p->cw;
+    d.Q = p->cov->Q;
+    d.yop = p->yop;
+    pl->max_chunks = std::max<int>(pl->max_chunks, (int)((p->P + kRedoCols - 1) / kRedoCols));
     d.table = p->table;
     d.lscale = p->lscale;
     d.n_pheno = p->P;
@@ -509,23 +590,25 @@ extern "C" tgw_status tgw_plan_create(const tgw_panel* const* panels, int32_t n_
   }
   pl->n_cb = (int)cbm.size();
   pl->n_cb_w = (int)cbw.size();
-  const int64_t per_marker = (int64_t)sizeof(uint4) + sizeof(MarkerStat) + (int64_t)n_panels * (kSlots + 1) * 4;
+  const int64_t per_marker = (int64_t)sizeof(uint4) + sizeof(MarkerStat) + (int64_t)n_panels * (kSlots + 3) * 4;
   int64_t MB = o.block_markers;
   if (MB == 0) MB = std::max<int64_t>(4096, std::min<int64_t>(1 << 20, (2ll << 30) / per_marker));
   MB = round_up(MB, 512);
   pl->MB = MB;
   pl->tail_cap = o.tail_capacity ? o.tail_capacity : (1 << 20);
 
-  hipError_t e = dmalloc(&pl->d_cb_main, cbm.size());
-  if (e == hipSuccess) e = dmalloc(&pl->d_cb_w, cbw.size());
-  if (e == hipSuccess) e = dmalloc(&pl->d_panels, pdv.size());
-  if (e == hipSuccess) e = dmalloc(&pl->d_outs, (size_t)n_panels);
-  if (e == hipSuccess) e = dmalloc(&pl->mlut, (size_t)MB);
-  if (e == hipSuccess) e = dmalloc(&pl->mstat, (size_t)MB);
-  if (e == hipSuccess) e = dmalloc(&pl->wws, (size_t)MB * n_panels * kSlots);
-  if (e == hipSuccess) e = dmalloc(&pl->invh, (size_t)MB * n_panels);
-  if (e == hipSuccess) e = dmalloc(&pl->tail_entries, (size_t)pl->tail_cap);
-  if (e == hipSuccess) e = dmalloc(&pl->tail_count, 1);
+  hipError_t e = dmalloc(pl->mem, &pl->d_cb_main, cbm.size());
+  if (e == hipSuccess) e = dmalloc(pl->mem, &pl->d_cb_w, cbw.size());
+  if (e == hipSuccess) e = dmalloc(pl->mem, &pl->d_panels, pdv.size());
+  if (e == hipSuccess) e = dmalloc(pl->mem, &pl->d_outs, (size_t)n_panels);
+  if (e == hipSuccess) e = dmalloc(pl->mem, &pl->mlut, (size_t)MB);
+  if (e == hipSuccess) e = dmalloc(pl->mem, &pl->mstat, (size_t)MB);
+  if (e == hipSuccess) e = dmalloc(pl->mem, &pl->wws, (size_t)MB * n_panels * kSlots);
+  if (e == hipSuccess) e = dmalloc(pl->mem, &pl->invh, (size_t)MB * n_panels);
+  if (e == hipSuccess) e = dmalloc(pl->mem, &pl->redo_entries, (size_t)MB * n_panels);
+  if (e == hipSuccess) e = dmalloc(pl->mem, &pl->redo_count, (size_t)n_panels);
+  if (e == hipSuccess) e = dmalloc(pl->mem, &pl->tail_entries, (size_t)pl->tail_cap);
+  if (e == hipSuccess) e = dmalloc(pl->mem, &pl->tail_count, 1);
   if (e == hipSuccess) e = hipMemcpy(pl->d_cb_main, cbm.data(), cbm.size() * sizeof(ColBlock), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(pl->d_cb_w, cbw.data(), cbw.size() * sizeof(ColBlock), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(pl->d_panels, pdv.data(), pdv.size() * sizeof(PanelDev), hipMemcpyHostToDevice);
@@ -636,6 +719,8 @@ static hipError_t enqueue_block_stats(tgw_plan* pl, const ScanCall& c, int64_t m
   sa.prec = pl->prec;
   sa.mlut = pl->mlut;
   sa.mstat = pl->mstat;
+  sa.redo_count = pl->redo_count;
+  sa.n_panels = pl->n_panels;
   hipError_t e = launch_stats(sa, s);
   if (e != hipSuccess) return e;
   GemmArgs a = base_args(pl, c, m0, nm);
@@ -650,7 +735,32 @@ static hipError_t enqueue_block_stats(tgw_plan* pl, const ScanCall& c, int64_t m
   e = launch_gemm(wgemm_tile(), wprec(pl->prec), pl->w_mode, a, g8 ? pl->grid_w8 : pl->grid_w, s, g8);
   if (e != hipSuccess) return e;
   return launch_finalize(pl->mstat, pl->wws, pl->invh, nm, pl->n_panels,
-                         f16_scaled(pl->prec) ? 1.0f / kF16Scale : 1.0f, s);
+                         f16_scaled(pl->prec) ? 1.0f / kF16Scale : 1.0f,
+                         RedoDev{pl->redo_entries, pl->redo_count, pl->MB}, s);
+}
+
+// the FP64 path of the block's covariate-collinear markers (after the main kernel)
+static hipError_t enqueue_redo(tgw_plan* pl, const ScanCall& c, int64_t m0, hipStream_t s) {
+  RedoArgs r{};
+  r.geno = c.geno;
+  r.row_bytes = c.row_bytes;
+  r.m0 = m0 - c.geno_row0;
+  r.n = pl->n;
+  r.n_pad = pl->n_pad;
+  r.n_chunks = pl->n_chunks;
+  r.code = c.code;
+  r.prec = pl->prec;
+  r.n_panels = pl->n_panels;
+  r.max_chunks = pl->max_chunks;
+  r.gunit = c.code == TGW_CODE_DOSAGE8 ? kDosage8Unit : 1.0f;
+  r.out_row0 = m0 - c.m_begin;
+  r.m_begin = c.m_begin;
+  r.mstat = pl->mstat;
+  r.panels = pl->d_panels;
+  r.outs = pl->d_outs;
+  r.hits = pl->hits;
+  r.redo = RedoDev{pl->redo_entries, pl->redo_count, pl->MB};
+  return launch_redo(r, pl->n_cu, s);
 }
 
 static hipError_t enqueue_main(tgw_plan* pl, const ScanCall& c, int64_t m0, int64_t nm, int tile, hipStream_t s) {
@@ -706,6 +816,7 @@ hipError_t tgw::enqueue_scan_rows(tgw_plan* pl, const ScanCall& c, int64_t m_lo,
     const int64_t nm = std::min(pl->MB, m_hi - m0);
     e = enqueue_block_stats(pl, c, m0, nm, s);
     if (e == hipSuccess) e = enqueue_main(pl, c, m0, nm, c.code == TGW_CODE_DOSAGE8 ? pl->tile8 : pl->tile, s);
+    if (e == hipSuccess) e = enqueue_redo(pl, c, m0, s);
   }
   return e;
 }
@@ -958,7 +1069,7 @@ extern "C" tgw_status tgw_debug_contract(tgw_plan* pl, const uint8_t* d_geno, in
 
 extern "C" tgw_status tgw_debug_marker_stats(tgw_plan* pl, const uint8_t* d_geno, int64_t n_markers,
                                              int64_t row_bytes, tgw_geno_code code, int64_t m_begin, int64_t m_end,
-                                             double* d_shift, double* d_mean, void* stream) {
+                                             double* d_shift, double* d_mean, double* d_scale, void* stream) {
   TGW_GUARD_BEGIN
   ScanCall c{d_geno, n_markers, row_bytes, (int)code, m_begin, m_end, nullptr, 0};
   tgw_status st = check_call(pl, c, false);
@@ -978,7 +1089,8 @@ extern "C" tgw_status tgw_debug_marker_stats(tgw_plan* pl, const uint8_t* d_geno
     sa.mstat = pl->mstat;
     HIP_TRY(launch_stats(sa, s));
     HIP_TRY(launch_debug_stats(pl->mstat, nm, d_shift ? d_shift + (m0 - m_begin) : nullptr,
-                               d_mean ? d_mean + (m0 - m_begin) : nullptr, s));
+                               d_mean ? d_mean + (m0 - m_begin) : nullptr,
+                               d_scale ? d_scale + (m0 - m_begin) : nullptr, s));
   }
   return TGW_OK;
   TGW_GUARD_END

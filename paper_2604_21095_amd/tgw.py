@@ -122,7 +122,25 @@ _dbg_contract = _sig("tgw_debug_contract", ctypes.c_int, _vp, _vp, _i64, _i64, c
                      _vp)
 _dbg_set_operand = _sig("tgw_debug_set_operand", ctypes.c_int, _vp, _vp, _i64, _vp)
 _dbg_stats = _sig("tgw_debug_marker_stats", ctypes.c_int, _vp, _vp, _i64, _i64, ctypes.c_int, _i64, _i64, _vp, _vp,
-                  _vp)
+                  _vp, _vp)
+_set_allocator = _sig("tgw_set_allocator", ctypes.c_int, _vp, _vp, _vp)
+
+
+class AllocCounts(ctypes.Structure):
+    """tgw_debug_alloc_counts: what the test allocator (debug_counting_allocator) recorded."""
+    _fields_ = [("n_alloc", _i64), ("n_free", _i64), ("bytes", _i64)]
+
+
+def debug_counting_allocator():
+    """Addresses of the library's counting test allocator (hipMalloc / hipFree that
+    record into an AllocCounts passed as ctx)."""
+    return (ctypes.cast(_lib.tgw_debug_counting_alloc, _vp), ctypes.cast(_lib.tgw_debug_counting_free, _vp))
+
+
+def set_allocator(alloc_fn=None, free_fn=None, ctx=None):
+    """Register C allocator functions (addresses of tgw_alloc_fn / tgw_free_fn) for the
+    device memory of handles made afterwards; no arguments restores hipMalloc / hipFree."""
+    _check(_set_allocator(alloc_fn, free_fn, ctx), "tgw_set_allocator")
 
 
 class TgwError(RuntimeError):
@@ -414,9 +432,10 @@ class Plan:
         g, nm, rb, code, m0, m1 = self._args(geno, m_begin, m_end, code)
         shift = torch.empty(m1 - m0, dtype=torch.float64, device="cuda")
         mean = torch.empty(m1 - m0, dtype=torch.float64, device="cuda")
-        _check(_dbg_stats(self._h, g, nm, rb, code, m0, m1, _ptr(shift), _ptr(mean), _stream(stream)),
+        scale = torch.empty(m1 - m0, dtype=torch.float64, device="cuda")
+        _check(_dbg_stats(self._h, g, nm, rb, code, m0, m1, _ptr(shift), _ptr(mean), _ptr(scale), _stream(stream)),
                "tgw_debug_marker_stats")
-        return shift, mean
+        return shift, mean, scale
 
     def __del__(self, _free=_plan_free):  # bound early: module globals are gone at interpreter exit
         if getattr(self, "_h", None):

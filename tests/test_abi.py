@@ -21,7 +21,7 @@ def test_library_exports_every_declared_symbol(tgw):
     assert "tgw_scan" in syms and "tgw_fit_covariates" in syms and "tgw_prepare_phenotypes" in syms
     missing = [s for s in syms if not hasattr(tgw._lib, s)]
     assert not missing, missing
-    assert tgw.abi_version() == 4
+    assert tgw.abi_version() == 5
 
 
 def test_header_is_plain_c(tmp_path):
@@ -39,7 +39,8 @@ def test_test_hooks_stay_out_of_the_product_header(tgw):
     text = open(HEADER).read()
     assert "tgw_debug_" not in text
     dbg = open(os.path.join(os.path.dirname(HEADER), "tgw_debug.h")).read()
-    for name in ("tgw_debug_contract", "tgw_debug_set_operand", "tgw_debug_marker_stats"):
+    for name in ("tgw_debug_contract", "tgw_debug_set_operand", "tgw_debug_marker_stats", "tgw_debug_counting_alloc",
+                 "tgw_debug_counting_free"):
         assert name in dbg and name in tgw.header_symbols()
 
 
@@ -71,6 +72,14 @@ def test_validation_before_any_device_call(tgw):
     assert tgw._tile_shape(-1, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)) == tgw.ERR_INVALID_ARG
     assert tgw._tile_shape(0, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)) == tgw.OK
     assert (a.value, b.value, c.value) == (512, 128, 4)
+    # the allocator hook takes both functions or neither
+    fa, ff = tgw.debug_counting_allocator()
+    assert tgw._set_allocator(fa, None, None) == tgw.ERR_INVALID_ARG
+    assert tgw._set_allocator(None, ff, None) == tgw.ERR_INVALID_ARG
+    counts = tgw.AllocCounts()
+    assert tgw._set_allocator(fa, ff, ctypes.byref(counts)) == tgw.OK
+    assert tgw._set_allocator(None, None, None) == tgw.OK
+    assert (counts.n_alloc, counts.n_free, counts.bytes) == (0, 0, 0)
     # freeing NULL handles is a no-op
     lib.tgw_plan_free(None)
     lib.tgw_panel_free(None)

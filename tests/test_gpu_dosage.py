@@ -52,7 +52,7 @@ def test_dosage8_contraction_exact_integers(tgw, precision, n, m, p, tile):
     plan = _debug_plan(tgw, n, V, precision, tile)
     g = torch.from_numpy(_rows(q)).cuda()
     S = plan.debug_contract(g, code=tgw.CODE_DOSAGE8).cpu().numpy().astype(np.float64)
-    shift, mean = [x.cpu().numpy() for x in plan.debug_marker_stats(g, code=tgw.CODE_DOSAGE8)]
+    shift, mean, _ = [x.cpu().numpy() for x in plan.debug_marker_stats(g, code=tgw.CODE_DOSAGE8)]
     np.testing.assert_array_equal(mean, q.astype(np.int64).sum(axis=1) / n)
     want_shift = np.rint(mean)
     want_shift[5] = 0.0
@@ -78,7 +78,7 @@ def test_dosage8_contraction_missing_value(tgw, precision):
     S = plan.debug_contract(g, code=tgw.CODE_DOSAGE8).cpu().numpy().astype(np.float64)
     if precision in F16_FORMS:
         S = S / tgw.F16_SCALE
-    shift, mean = [x.cpu().numpy() for x in plan.debug_marker_stats(g, code=tgw.CODE_DOSAGE8)]
+    shift, mean, _ = [x.cpu().numpy() for x in plan.debug_marker_stats(g, code=tgw.CODE_DOSAGE8)]
     obs = q < 255
     mu = np.where(obs, q, 0).astype(np.int64).sum(1) / obs.sum(1)
     np.testing.assert_allclose(mean, mu, rtol=1e-15)

@@ -12,12 +12,12 @@ import torch
 import oracle
 from synth import (cohort_spec, causal_markers, geno_codes_np, pack_codes_np, packed_rows_torch, panel_inputs,
                    row_bytes_for)
-from tests.gpu_common import R_TOL, compare, cohort_arrays, decode_codes, gpu_scan, lib, oracle_scan, say
+from tests.gpu_common import (R_TOL, bf16_round, compare, cohort_arrays, decode_codes, gpu_scan, lib, oracle_scan,
+                               recentre, say)
 
 pytestmark = pytest.mark.gpu
 
 PRECS = ["split", "split16", "split8", "fp32"]
-GRID = {"split": 64, "split16": 512, "split8": 512, "fp32": 64}
 F16_FORMS = ("split16", "split8")  # operands stored as 2^12 y
 
 
@@ -26,13 +26,6 @@ def tgw():
     t = lib()
     t.init()
     return t
-
-
-def _bf16_round(x: np.ndarray) -> np.ndarray:
-    """Round-to-nearest-even to bfloat16 (via float32), returned as float64."""
-    f = np.asarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
-    f = (f + 0x7FFF + ((f >> 16) & 1)) >> 16 << 16
-    return f.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
 # ---------------------------------------------------------------------------
@@ -54,15 +47,16 @@ def test_contraction_exact_integers(tgw, precision, n, m, p, tile):
     plan = tgw.Plan([panel], tile=tile)
     g = torch.from_numpy(packed).cuda()
     S = plan.debug_contract(g).cpu().numpy().astype(np.float64)
-    shift, mean = [x.cpu().numpy() for x in plan.debug_marker_stats(g)]
+    shift, mean, gs = [x.cpu().numpy() for x in plan.debug_marker_stats(g)]
     np.testing.assert_array_equal(mean, codes.mean(axis=1))
-    grid = GRID[precision]
-    want_shift = np.rint(grid * codes.mean(axis=1)) / grid
-    want_shift[5] = 0.0  # degenerate (monomorphic) markers are not re-centred
+    ok = np.ones(m, dtype=bool)
+    ok[5] = False  # degenerate (monomorphic) markers are not re-centred
+    want_shift, want_gs, obs_val, _ = recentre(codes.mean(axis=1), ok, precision)
     np.testing.assert_array_equal(shift, want_shift)
+    np.testing.assert_array_equal(gs, want_gs)
     if precision in F16_FORMS:
         S = S / tgw.F16_SCALE  # the FP16 forms store 2^12 times the operand
-    A = codes.astype(np.float64) - shift[:, None]
+    A = np.take_along_axis(obs_val, codes.astype(np.int64), axis=1)  # gs (g - c), exact
     want = A @ V.astype(np.float64)
     assert np.array_equal(want, want.astype(np.float32).astype(np.float64))  # exactly representable
     np.testing.assert_array_equal(S, want)
@@ -85,20 +79,27 @@ def test_contraction_missing_value(tgw, precision):
     S = plan.debug_contract(g).cpu().numpy().astype(np.float64)
     if precision in F16_FORMS:
         S = S / tgw.F16_SCALE
-    shift, mean = [x.cpu().numpy() for x in plan.debug_marker_stats(g)]
+    shift, mean, gs = [x.cpu().numpy() for x in plan.debug_marker_stats(g)]
     obs = codes < 3
     mu = np.where(obs, codes, 0).sum(1) / obs.sum(1)
     np.testing.assert_allclose(mean, mu, rtol=1e-15)
-    vm = mu - shift
+    ok = np.array([len(set(row[row < 3].tolist())) > 1 for row in codes])
+    want_shift, want_gs, obs_val, vm = recentre(mean, ok, precision)
+    np.testing.assert_array_equal(shift, want_shift)
+    np.testing.assert_array_equal(gs, want_gs)
     if precision == "split":
-        vm_op, bound = _bf16_round(vm), 2.0 ** -16
+        # at most 2^-9 |mu - c| per genotype unit; 2^-16 with the nearest multiple of 1/64
+        vm_op, bound = bf16_round(vm), 2.0 ** -17 * gs
     elif precision in F16_FORMS:
         vm_op, bound = vm.astype(np.float16).astype(np.float64), 2.0 ** -21
     else:
         vm_op, bound = vm.astype(np.float32).astype(np.float64), 2.0 ** -30
     assert np.all(np.abs(vm - vm_op) <= bound)
-    np.testing.assert_array_equal(shift, np.rint(GRID[precision] * mu) / GRID[precision])
-    A = np.where(obs, codes - shift[:, None], vm_op[:, None])
+    if precision == "split":
+        err = np.abs(vm - vm_op) / gs
+        say(f"BF16 missing-value error per genotype unit: max {err.max():.3g}, median {np.median(err):.3g}")
+        assert np.median(err) < 2.0 ** -22
+    A = np.where(obs, np.take_along_axis(obs_val, np.minimum(codes, 2).astype(np.int64), axis=1), vm_op[:, None])
     want = A @ V.astype(np.float64)
     scale = np.abs(A) @ np.abs(V.astype(np.float64)) + 1.0
     assert np.max(np.abs(S - want) / scale) < 1e-6
@@ -128,7 +129,7 @@ def test_contraction_fp8_lo_term(tgw):
     plan = tgw.Plan([panel])
     g = torch.from_numpy(pack_codes_np(codes, row_bytes_for(n))).cuda()
     S = plan.debug_contract(g).cpu().numpy().astype(np.float64)
-    shift, _ = [x.cpu().numpy() for x in plan.debug_marker_stats(g)]
+    shift, _, _ = [x.cpu().numpy() for x in plan.debug_marker_stats(g)]
     obs = codes < 3
     mu = np.where(obs, codes, 0).sum(1) / obs.sum(1)
     A16 = np.where(obs, codes - shift[:, None], (mu - shift)[:, None].astype(np.float16).astype(np.float64))
@@ -462,7 +463,8 @@ def test_cfg3_bench_configuration(tgw, precision):
     compare(got, ref, ref["df"], f"cfg3 {precision} ")
 
 
-def test_cfg5_batching_form_sampled(tgw):
+@pytest.mark.parametrize("precision", ["split", "split8"])
+def test_cfg5_batching_form_sampled(tgw, precision):
     """Batching form at full size: 64 panels of uneven P (log-uniform 32..4096) and
     K (3..20) sharing N=23,000 x M=200,000 genotypes, all in one plan; sampled
     markers of every panel are checked against the oracle."""
@@ -470,7 +472,7 @@ def test_cfg5_batching_form_sampled(tgw):
     M, n = spec.n_markers, spec.n_samples
     rows = np.unique(np.concatenate([np.arange(0, 24), np.arange(M // 2, M // 2 + 24),
                                      np.arange(M - 24, M), causal_markers(spec)[:8]]))
-    say(f"case: cfg5 batching, {len(spec.panels)} panels, {len(rows)} sampled markers")
+    say(f"case: cfg5 batching {precision}, {len(spec.panels)} panels, {len(rows)} sampled markers")
     codes = geno_codes_np(spec, rows)
     g = torch.from_numpy(pack_codes_np(codes, row_bytes_for(n))).cuda()
     Cs, Ys, panels = [], [], []
@@ -479,14 +481,14 @@ def test_cfg5_batching_form_sampled(tgw):
         Cs.append(C)
         Ys.append(Y)
         cov = tgw.fit_covariates(torch.from_numpy(C).cuda())
-        panels.append(tgw.prepare_phenotypes(cov, torch.from_numpy(Y).cuda(), "split"))
+        panels.append(tgw.prepare_phenotypes(cov, torch.from_numpy(Y).cuda(), precision))
     plan = tgw.Plan(panels)
     outs = tgw.scan(plan, g, names=("r", "t", "nlog10p"))
     plan.check()
     worst = 0.0
     for j in range(len(spec.panels)):
         ref = oracle_scan(codes, Cs[j], Ys[j])
-        errs = compare({k: v.cpu().numpy() for k, v in outs[j].items()}, ref, ref["df"], f"cfg5 panel {j} ")
+        errs = compare({k: v.cpu().numpy() for k, v in outs[j].items()}, ref, ref["df"], f"cfg5 {precision} panel {j} ")
         worst = max(worst, errs["r"])
     say(f"cfg5 worst |dr| over panels: {worst:.3g}")
 
@@ -511,19 +513,21 @@ def test_phenotype_dependent_missingness(tgw, precision):
     res, _, _ = gpu_scan(C, [Y], packed, precision)
     ref = oracle_scan(codes, C, Y)
     if precision == "split":
-        # BF16 carries the imputed value to 2^-16: |dr| <= 2^-16 |sum_miss y~| / ||g_res||,
-        # here up to ~5e-6 (within |dr| <= 1e-5, but -log10 p of moderate tests moves
-        # by up to ~2e-4 relative); FP16 split and FP32 meet the full criteria.
+        # BF16 carries the imputed value to within e_m per genotype unit (the
+        # rounding of the re-centred missing value, per marker), so
+        # |dr| <= e_m |sum_miss y~| / ||g_res|| plus the FP32 accumulation
         G = decode_codes(codes)
         miss = np.isnan(G)
+        mu = np.nanmean(G, axis=1)
+        _, gs, _, vm = recentre(mu, np.ones(m, dtype=bool), precision)
+        e_m = np.abs(bf16_round(vm) - vm) / gs
+        say(f"BF16 missing-value error per genotype unit: max {e_m.max():.3g} (nearest 1/64: <= {2.0 ** -16:.3g})")
         Yt = oracle.prepare_panel(Y.astype(np.float64), oracle.covariate_basis(C))[0]
-        bound = 2.0 ** -16 * np.abs(miss.astype(np.float64) @ Yt) / ref["h"][:, None]
+        bound = e_m[:, None] * np.abs(miss.astype(np.float64) @ Yt) / ref["h"][:, None]
         dr = np.abs(res[0]["r"] - ref["r"])
         ok = np.isfinite(ref["r"])
         assert np.all(dr[ok] <= bound[ok] + 2e-6), float(np.max(dr[ok] - bound[ok]))
-        compare(res[0], ref, ref["df"], f"dependent missingness {precision} ", p_tol=5e-4)
-    else:
-        compare(res[0], ref, ref["df"], f"dependent missingness {precision} ")
+    compare(res[0], ref, ref["df"], f"dependent missingness {precision} ")
 
 
 @pytest.fixture(scope="module")
