@@ -313,6 +313,31 @@ tgw_status tgw_plan_check(tgw_plan* plan, void* stream, int64_t* n_tail);
 tgw_status tgw_plan_profile(tgw_plan* plan, int32_t enable);
 tgw_status tgw_plan_profile_read(tgw_plan* plan, void* stream, double* main_ms, int64_t* launches);
 
+/* ---- scan without a plan, allocating nothing --------------------------------
+ * For callers that cannot allocate device memory at scan time (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * tgw_scan over the given panels without a plan.  Everything a plan holds
+ * (column-block tables, per-panel constants, output table, per-block
+ * workspace, the FP64 list of collinear markers, the tail list) lives in a
+ * static device array of 64 MiB that every GPU the library runs on holds
+ * until the process ends; the call allocates nothing and does not
+ * synchronize.  Same arguments and results as tgw_scan (the panels' order is
+ * the outputs' order), with these differences:
+ *   - at most 32 panels and 2^20 phenotype columns in all (TGW_ERR_SHAPE);
+ *     the marker block is the largest multiple of 512 markers whose
+ *     workspace fits (330,240 markers for one panel, 13,824 for 32);
+ *   - tile: the tile shape index (< 0: shape 0; 8-bit dosages: shape 2);
+ *     no autotuning, no hit list, no profiling;
+ *   - the tail list holds 65,536 tests; d_n_tail (device, may be NULL)
+ *     receives the number of tail tests the call found: above 65,536 the
+ *     excess keep the table's lower bound at |t| = 40;
+ *   - calls on one GPU share the array and leave its contents behind: two
+ *     calls that overlap on one GPU (streams, threads) race; host threads
+ *     are serialized while they enqueue. */
+tgw_status tgw_scan_static(const tgw_panel* const* panels, int32_t n_panels, const uint8_t* d_geno,
+                           int64_t n_markers, int64_t row_bytes, tgw_geno_code code, int64_t m_begin, int64_t m_end,
+                           const tgw_outputs* outs, int32_t tile, unsigned long long* d_n_tail, void* stream);
+
 /* ---- graph capture ---------------------------------------------------------
  * Captures one tgw_scan call (same arguments) into an instantiated HIP graph;
  * tgw_graph_launch replays it on `stream`.  The graph refers to the plan's

@@ -81,6 +81,7 @@ struct PanelDev {
   const uint8_t* lscale; // FP8 form: E8M0 scale of each column's lo term (NULL otherwise)
   const double* Q;      // covariate basis, [q][n_pad] FP64 (the FP64 path of collinear markers)
   const void* yop;      // operand base (column 0, chunk 0)
+  const void* wop;      // the covariates' Q^T g operand of this precision (packed hi|lo blocks, or FP32)
   int64_t n_pheno;
   float df;
   float sqrt_df;

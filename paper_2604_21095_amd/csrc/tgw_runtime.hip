@@ -39,9 +39,11 @@ struct DevInfo {
   int n_cu = 0;
   std::string arch;
   bool gfx950 = false;
+  char* scratch = nullptr;  // this device's copy of `scratch` (tgw_scan_static)
 };
 
 static std::mutex g_dev_mu;
+static hipError_t static_scratch_address(char** p);  // with the device current
 static std::map<int, DevInfo> g_dev;
 
 static tgw_status device_info(int* dev_out, DevInfo* info) {
@@ -56,12 +58,24 @@ static tgw_status device_info(int* dev_out, DevInfo* info) {
     d.n_cu = p.multiProcessorCount;
     d.arch = p.gcnArchName;
     d.gfx950 = d.arch.rfind("gfx950", 0) == 0;
+    if (d.gfx950) HIP_TRY(static_scratch_address(&d.scratch));
     it = g_dev.emplace(dev, d).first;
   }
   if (!it->second.gfx950)
     return fail(TGW_ERR_UNSUPPORTED, "device architecture " + it->second.arch + " is not gfx950");
   if (dev_out) *dev_out = dev;
   if (info) *info = it->second;
+  return TGW_OK;
+}
+
+// the current device's CU count and static scratch, without copying DevInfo
+static tgw_status device_basics(int* dev, int* n_cu, char** scratch) {
+  tgw_status st = device_info(dev, nullptr);
+  if (st != TGW_OK) return st;
+  std::lock_guard<std::mutex> lk(g_dev_mu);
+  const DevInfo& d = g_dev.find(*dev)->second;
+  *n_cu = d.n_cu;
+  *scratch = d.scratch;
   return TGW_OK;
 }
 
@@ -159,7 +173,27 @@ struct tgw_panel {
   float* cw = nullptr;
   float4* table = nullptr;
   uint8_t* lscale = nullptr;  // FP8 lo form: E8M0 scale per column
+  PanelDev* d_dev = nullptr;  // its PanelDev on the device (tables of tgw_scan_static)
 };
+
+// the per-panel constants the kernels read
+static PanelDev panel_dev(const tgw_panel* p) {
+  PanelDev d{};
+  d.scale = p->scale;
+  d.invny = p->invny;
+  d.cw = p->cw;
+  d.table = p->table;
+  d.lscale = p->lscale;
+  d.Q = p->cov->Q;
+  d.yop = p->yop;
+  d.wop = wprec(p->prec) != kFP32 ? p->cov->wop_hl[wprec(p->prec)] : p->cov->wop_fp32;
+  d.n_pheno = p->P;
+  d.df = (float)p->df;
+  d.sqrt_df = (float)std::sqrt((double)p->df);
+  d.inv_sqrt_df = (float)(1.0 / std::sqrt((double)p->df));
+  d.q = p->cov->q;
+  return d;
+}
 
 struct tgw_plan {
   DevAllocator mem;
@@ -335,6 +369,7 @@ extern "C" void tgw_panel_free(tgw_panel* p) {
   dev_free(p->mem, p->cw, nullptr);
   dev_free(p->mem, p->table, nullptr);
   dev_free(p->mem, p->lscale, nullptr);
+  dev_free(p->mem, p->d_dev, nullptr);
   delete p;
 }
 
@@ -376,6 +411,7 @@ extern "C" tgw_status tgw_prepare_phenotypes(const tgw_covariates* cov, int64_t 
   if (e == hipSuccess) e = dmalloc(A, &p->cw, (size_t)p->P_pad * kSlots, s);
   if (e == hipSuccess) e = dmalloc(A, &p->table, kTabIntervals, s);
   if (e == hipSuccess) e = dmalloc(A, &flags, 1, s);
+  if (e == hipSuccess) e = dmalloc(A, &p->d_dev, 1, s);
   if (e == hipSuccess) e = hipMemsetAsync(p->yop, 0, op_bytes, s);
   if (e == hipSuccess) e = hipMemsetAsync(p->scale, 0, p->P_pad * sizeof(float), s);
   if (e == hipSuccess) e = hipMemsetAsync(p->invny, 0, p->P_pad * sizeof(float), s);
@@ -385,6 +421,8 @@ extern "C" tgw_status tgw_prepare_phenotypes(const tgw_covariates* cov, int64_t 
     e = launch_prep(d_Y, y_is_fp64, ldy, cov->n, cov->n_pad, n_pheno, cov->Q, cov->q, p->prec, p->yop, p->scale,
                     p->invny, p->cw, p->lscale, flags, s);
   if (e == hipSuccess) e = launch_table(p->table, (double)p->df, s);
+  const PanelDev pd = panel_dev(p);
+  if (e == hipSuccess) e = hipMemcpyAsync(p->d_dev, &pd, sizeof(pd), hipMemcpyHostToDevice, s);
   int32_t hf = 0;
   if (e == hipSuccess) e = hipMemcpyAsync(&hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -572,21 +610,8 @@ extern "C" tgw_status tgw_plan_create(const tgw_panel* const* panels, int32_t n_
       w.ncol = kSlots;
       cbw.push_back(w);
     }
-    PanelDev d{};
-    d.scale = p->scale;
-    d.invny = p->invny;
-    d.cw = p->cw;
-    d.Q = p->cov->Q;
-    d.yop = p->yop;
     pl->max_chunks = std::max<int>(pl->max_chunks, (int)((p->P + kRedoCols - 1) / kRedoCols));
-    d.table = p->table;
-    d.lscale = p->lscale;
-    d.n_pheno = p->P;
-    d.df = (float)p->df;
-    d.sqrt_df = (float)std::sqrt((double)p->df);
-    d.inv_sqrt_df = (float)(1.0 / std::sqrt((double)p->df));
-    d.q = p->cov->q;
-    pdv.push_back(d);
+    pdv.push_back(panel_dev(p));
   }
   pl->n_cb = (int)cbm.size();
   pl->n_cb_w = (int)cbw.size();
@@ -1022,6 +1047,250 @@ extern "C" void tgw_graph_free(tgw_graph* g) {
   if (g->exec) (void)hipGraphExecDestroy(g->exec);
   if (g->graph) (void)hipGraphDestroy(g->graph);
   delete g;
+}
+
+// ---------------------------------------------------------------------------
+// allocation-free scan: tgw_scan_static keeps everything tgw_scan keeps in a
+// plan (column-block tables, per-panel constants, output table, per-block
+// workspace, FP64 lists, tail list) in `scratch`, a static device array that
+// every GPU the library runs on holds until the process ends.  Host code
+// never uses the array's name as an address: each device's address comes
+// from hipGetSymbolAddress (device_info, once per device) and is kept in
+// DevInfo.  Calls on one GPU share the array: a call leaves its contents
+// behind, everything a call reads it writes first (the tables and the tail
+// count by static_setup_kernel, the FP64 list counts by the stats kernel of
+// each block), and calls that overlap on one GPU race.
+// ---------------------------------------------------------------------------
+constexpr size_t kStaticBytes = size_t(64) << 20;
+constexpr int kStaticPanels = kMaxPanelsPerBind;  // 32
+constexpr int kStaticColBlocks = 32768;           // 2^20 phenotype columns in all
+constexpr int kStaticTail = 1 << 16;
+static __device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+static hipError_t static_scratch_address(char** p) {
+  void* a = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+  *p = e == hipSuccess ? (char*)a : nullptr;
+  return e;
+}
+
+namespace {
+struct StaticSetupArgs {
+  const PanelDev* pd[kStaticPanels];  // each panel's device copy
+  OutDev outs[kStaticPanels];
+  int32_t cb_off[kStaticPanels + 1];  // main column blocks before panel j
+  int32_t w_off[kStaticPanels + 1];   // Q^T g column blocks before panel j
+  int32_t n_panels, n_chunks, prec, hl;
+  ColBlock* cb_main;
+  ColBlock* cb_w;
+  PanelDev* panels;
+  OutDev* outs_dev;
+  unsigned long long* tail_count;
+};
+static_assert(sizeof(StaticSetupArgs) <= 4096, "kernel argument size");
+
+// the tables tgw_plan_create builds on the host, built here from the
+// panels' device constants; also clears the tail count
+__global__ void static_setup_kernel(StaticSetupArgs a) {
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nt = gridDim.x * blockDim.x;
+  if (tid == 0) a.tail_count[0] = 0ull;
+  for (int j = tid; j < a.n_panels; j += nt) {
+    const PanelDev pd = *a.pd[j];
+    a.panels[j] = pd;
+    a.outs_dev[j] = a.outs[j];
+    const int nb = a.w_off[j + 1] - a.w_off[j];
+    for (int b = 0; b < nb; ++b) {
+      ColBlock w{};
+      w.op = (const char*)pd.wop + (size_t)b * a.n_chunks * kBlockBytes;
+      w.panel = j;
+      w.col0 = j * kSlots + b * kHLSlots;
+      w.ncol = (a.hl && nb > 1) ? kHLSlots : kSlots;
+      a.cb_w[a.w_off[j] + b] = w;
+    }
+  }
+  for (int k = tid; k < a.cb_off[a.n_panels]; k += nt) {
+    int j = 0;
+    while (k >= a.cb_off[j + 1]) ++j;
+    const int b = k - a.cb_off[j];
+    const PanelDev* pd = a.pd[j];
+    ColBlock c{};
+    c.op = (const char*)pd->yop + (size_t)b * a.n_chunks * block_bytes(a.prec);
+    c.panel = j;
+    c.col0 = b * kColBlock;
+    c.ncol = (int32_t)std::min<int64_t>(kColBlock, pd->n_pheno - (int64_t)b * kColBlock);
+    a.cb_main[k] = c;
+  }
+}
+
+__global__ void static_tail_count_kernel(unsigned long long* dst, const unsigned long long* src) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = *src;
+}
+
+// the plan tgw_scan_static runs through, per device; its buffers point into
+// that device's scratch (made once, with room for kStaticPanels panels, so
+// that filling it in allocates nothing)
+struct StaticState {
+  std::mutex mu;
+  tgw_plan plan;
+};
+std::mutex g_static_mu;
+std::map<int, StaticState*> g_static;  // never freed: lives as long as the scratch
+
+StaticState* static_state(int dev) {
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  auto it = g_static.find(dev);
+  if (it != g_static.end()) return it->second;
+  auto* s = new StaticState();
+  s->plan.panels.reserve(kStaticPanels);
+  s->plan.grid_main.reserve(16);
+  s->plan.grid_main8.reserve(16);
+  g_static.emplace(dev, s);
+  return s;
+}
+}  // namespace
+
+extern "C" tgw_status tgw_scan_static(const tgw_panel* const* panels, int32_t n_panels, const uint8_t* d_geno,
+                                      int64_t n_markers, int64_t row_bytes, tgw_geno_code code, int64_t m_begin,
+                                      int64_t m_end, const tgw_outputs* outs, int32_t tile,
+                                      unsigned long long* d_n_tail, void* stream) {
+  TGW_GUARD_BEGIN
+  if (!panels || n_panels < 1) return fail(TGW_ERR_INVALID_ARG, "need at least one panel");
+  if (n_panels > kStaticPanels) return fail(TGW_ERR_SHAPE, "tgw_scan_static takes at most 32 panels");
+  for (int j = 0; j < n_panels; ++j)
+    if (!panels[j]) return fail(TGW_ERR_INVALID_ARG, "NULL panel");
+  const tgw_panel* p0 = panels[0];
+  for (int j = 1; j < n_panels; ++j) {
+    if (panels[j]->cov->n != p0->cov->n) return fail(TGW_ERR_SHAPE, "panels differ in n_samples");
+    if (panels[j]->prec != p0->prec) return fail(TGW_ERR_INVALID_ARG, "panels differ in precision");
+    if (panels[j]->cov->device != p0->cov->device) return fail(TGW_ERR_INVALID_ARG, "panels on different devices");
+  }
+  if (tile >= n_tile_shapes()) return fail(TGW_ERR_INVALID_ARG, "tile index out of range");
+  int dev = 0, n_cu = 0;
+  char* base = nullptr;
+  tgw_status st = device_basics(&dev, &n_cu, &base);
+  if (st != TGW_OK) return st;
+  if (dev != p0->cov->device) return fail(TGW_ERR_INVALID_ARG, "current device differs from the panels'");
+  if (!base) return fail(TGW_ERR_DEVICE, "no static scratch on this device");
+
+  // tables: sizes and offsets
+  const int prec = p0->prec;
+  const bool hl = wprec(prec) != kFP32;
+  StaticSetupArgs sa{};
+  int n_cb = 0, n_cbw = 0, max_chunks = 0;
+  for (int j = 0; j < n_panels; ++j) {
+    const tgw_panel* p = panels[j];
+    sa.pd[j] = p->d_dev;
+    sa.cb_off[j] = n_cb;
+    sa.w_off[j] = n_cbw;
+    n_cb += (int)std::min<int64_t>(p->P_pad / kColBlock, kStaticColBlocks + 1);
+    n_cbw += hl ? hl_blocks(p->cov->q) : 1;
+    max_chunks = std::max<int>(max_chunks, (int)((p->P + kRedoCols - 1) / kRedoCols));
+    if (n_cb > kStaticColBlocks)
+      return fail(TGW_ERR_SHAPE, "tgw_scan_static takes at most 2^20 phenotype columns in all");
+  }
+  sa.cb_off[n_panels] = n_cb;
+  sa.w_off[n_panels] = n_cbw;
+
+  // carve the scratch: tables and tail list, then the largest marker block
+  // (a multiple of 512) whose workspace fits in the rest
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    off = (off + 255) & ~size_t(255);
+    char* q = base + off;
+    off += bytes;
+    return q;
+  };
+  ColBlock* cb_main = (ColBlock*)take(sizeof(ColBlock) * kStaticColBlocks);
+  ColBlock* cb_w = (ColBlock*)take(sizeof(ColBlock) * 2 * kStaticPanels);
+  PanelDev* pdev = (PanelDev*)take(sizeof(PanelDev) * kStaticPanels);
+  OutDev* odev = (OutDev*)take(sizeof(OutDev) * kStaticPanels);
+  unsigned long long* tail_count = (unsigned long long*)take(sizeof(unsigned long long));
+  TailEntry* tail = (TailEntry*)take(sizeof(TailEntry) * kStaticTail);
+  uint32_t* redo_count = (uint32_t*)take(sizeof(uint32_t) * kStaticPanels);
+  const size_t per_marker = sizeof(uint4) + sizeof(MarkerStat) + (size_t)n_panels * (kSlots + 3) * 4;
+  const size_t avail = kStaticBytes - off - 6 * 256;
+  const int64_t MB = (int64_t)(avail / per_marker) / 512 * 512;
+  if (MB < 512) return fail(TGW_ERR_SHAPE, "static scratch too small");
+  uint4* mlut = (uint4*)take(sizeof(uint4) * MB);
+  MarkerStat* mstat = (MarkerStat*)take(sizeof(MarkerStat) * MB);
+  float* wws = (float*)take(sizeof(float) * MB * n_panels * kSlots);
+  float2* invh = (float2*)take(sizeof(float2) * MB * n_panels);
+  int32_t* redo_entries = (int32_t*)take(sizeof(int32_t) * MB * n_panels);
+  if (off > kStaticBytes) return fail(TGW_ERR_SHAPE, "static scratch too small");
+
+  StaticState* S = static_state(dev);
+  std::lock_guard<std::mutex> lk(S->mu);
+  tgw_plan& pl = S->plan;
+  pl.panels.assign(panels, panels + n_panels);  // capacity reserved: no allocation
+  pl.device = dev;
+  pl.prec = prec;
+  pl.n_cu = n_cu;
+  pl.n = p0->cov->n;
+  pl.n_pad = p0->cov->n_pad;
+  pl.n_chunks = p0->cov->n_chunks;
+  pl.n_panels = n_panels;
+  pl.n_cb = n_cb;
+  pl.n_cb_w = n_cbw;
+  pl.MB = MB;
+  pl.d_cb_main = cb_main;
+  pl.d_cb_w = cb_w;
+  pl.d_panels = pdev;
+  pl.d_outs = odev;
+  pl.mlut = mlut;
+  pl.mstat = mstat;
+  pl.wws = wws;
+  pl.invh = invh;
+  pl.redo_entries = redo_entries;
+  pl.redo_count = redo_count;
+  pl.max_chunks = max_chunks;
+  pl.tail_entries = tail;
+  pl.tail_count = tail_count;
+  pl.tail_cap = kStaticTail;
+  pl.hits = HitDev{};
+  pl.w_mode = hl ? kRawHL : kRaw;
+  pl.profile = false;
+  pl.tile = tile >= 0 ? tile : 0;
+  pl.tile8 = tile >= 0 ? tile : 2;
+  pl.grid_main.clear();
+  pl.grid_main8.clear();
+  for (int i = 0; i < n_tile_shapes(); ++i) pl.grid_main.push_back(gemm_grid(i, prec, kTest, n_cu));
+  pl.grid_w = gemm_grid(wgemm_tile(), wprec(prec), pl.w_mode, n_cu);
+  if (g8_supported(prec)) {
+    for (int i = 0; i < n_tile_shapes(); ++i) pl.grid_main8.push_back(gemm_grid(i, prec, kTest, n_cu, true));
+    pl.grid_w8 = gemm_grid(wgemm_tile(), wprec(prec), pl.w_mode, n_cu, true);
+  }
+
+  ScanCall c{d_geno, n_markers, row_bytes, (int)code, m_begin, m_end, outs, 0};
+  st = check_call(&pl, c, true);
+  if (st != TGW_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  for (int j = 0; j < n_panels; ++j) {
+    const tgw_outputs& o = outs[j];
+    sa.outs[j] = OutDev{o.r, o.beta, o.se, o.t, o.nlog10p, o.ld, o.best};
+  }
+  sa.n_panels = n_panels;
+  sa.n_chunks = pl.n_chunks;
+  sa.prec = prec;
+  sa.hl = hl ? 1 : 0;
+  sa.cb_main = cb_main;
+  sa.cb_w = cb_w;
+  sa.panels = pdev;
+  sa.outs_dev = odev;
+  sa.tail_count = tail_count;
+  hipLaunchKernelGGL(static_setup_kernel, dim3((unsigned)std::max(1, std::min(64, (n_cb + 255) / 256))), dim3(256),
+                     0, s, sa);
+  HIP_TRY(hipGetLastError());
+  if (m_begin < m_end) {
+    HIP_TRY(enqueue_scan_rows(&pl, c, m_begin, m_end, s));
+    HIP_TRY(enqueue_scan_end(&pl, m_begin, s));
+  }
+  if (d_n_tail) {
+    hipLaunchKernelGGL(static_tail_count_kernel, dim3(1), dim3(64), 0, s, d_n_tail, tail_count);
+    HIP_TRY(hipGetLastError());
+  }
+  return TGW_OK;
+  TGW_GUARD_END
 }
 
 // ---------------------------------------------------------------------------

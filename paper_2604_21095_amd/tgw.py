@@ -124,6 +124,8 @@ _dbg_set_operand = _sig("tgw_debug_set_operand", ctypes.c_int, _vp, _vp, _i64, _
 _dbg_stats = _sig("tgw_debug_marker_stats", ctypes.c_int, _vp, _vp, _i64, _i64, ctypes.c_int, _i64, _i64, _vp, _vp,
                   _vp, _vp)
 _set_allocator = _sig("tgw_set_allocator", ctypes.c_int, _vp, _vp, _vp)
+_scan_static = _sig("tgw_scan_static", ctypes.c_int, ctypes.POINTER(_vp), _i32, _vp, _i64, _i64, ctypes.c_int, _i64,
+                    _i64, ctypes.POINTER(Outputs), _i32, _vp, _vp)
 
 
 class AllocCounts(ctypes.Structure):
@@ -529,3 +531,18 @@ def scan(plan: Plan, geno, outs=None, m_begin=0, m_end=None, code=CODE_DOSAGE, s
         outs = make_outputs([p.n_pheno for p in plan.panels], m_end - m_begin, names)
     plan.scan(geno, outs, m_begin, m_end, code, stream)
     return outs
+
+
+def scan_static(panels: Sequence[Panel], geno, outs, m_begin=0, m_end=None, code=CODE_DOSAGE, tile=-1,
+                n_tail: Optional[torch.Tensor] = None, stream=None):
+    """tgw_scan_static: the scan without a plan, its workspace in the library's
+    static device array (nothing allocated); n_tail (int64 device scalar, optional)
+    receives the number of extreme-tail tests."""
+    hs = (ctypes.c_void_p * len(panels))(*[p.handle.value for p in panels])
+    _dev_check(geno)
+    if geno.dtype != torch.uint8 or geno.dim() != 2 or not geno.is_contiguous():
+        raise ValueError("geno must be a contiguous (n_markers, row_bytes) uint8 tensor")
+    m_end = geno.shape[0] if m_end is None else m_end
+    arr = _outs_array(outs, panels, m_end - m_begin)
+    _check(_scan_static(hs, len(panels), _ptr(geno), geno.shape[0], geno.shape[1], code, m_begin, m_end, arr, tile,
+                        _ptr(n_tail), _stream(stream)), "tgw_scan_static")
