@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define TGW_ABI_VERSION 5
+#define TGW_ABI_VERSION 6
 
 typedef enum {
   TGW_OK = 0,
@@ -137,7 +137,21 @@ typedef struct tgw_graph tgw_graph;           /* a captured tgw_scan call     */
  *            The caller zeroes it before the first scan; scans merge by
  *            maximum, so marker ranges may be split over calls (markers
  *            < 2^32).  NaN tests never enter; 0 means none.  Independent of
- *            the dense arrays, which may all be NULL. */
+ *            the dense arrays, which may all be NULL.
+ *   topk     optional reduced output (same passage: ranking loci per
+ *            phenotype): device array of n_pheno x topk_k words, row p
+ *            holding phenotype p's topk_k tests with the largest |t| (hence
+ *            the largest -log10 p at the panel's fixed df) over every marker
+ *            scanned into it, in decreasing order, each packed as
+ *            (IEEE bits of |t|) << 32 | (0xffffffff - marker) with the
+ *            absolute marker index (equal |t|: the smaller marker first);
+ *            0 = empty slot.  tgw_topk_read turns the words into -log10 p
+ *            (FP64) and marker indices.  The caller zeroes it before the
+ *            first scan; later scans merge into it, so marker ranges may be
+ *            split over calls, but must not overlap (a marker scanned twice
+ *            would be listed twice).  NaN tests never enter; |t| is exact
+ *            for |t| > 40 as well (FP32).  1 <= topk_k <= 64.
+ *   topk_k   entries per phenotype of topk (ignored when topk is NULL). */
 typedef struct {
   float* r;
   float* beta;
@@ -146,6 +160,9 @@ typedef struct {
   float* nlog10p;
   int64_t ld;
   unsigned long long* best;
+  unsigned long long* topk;
+  int32_t topk_k;
+  int32_t reserved;
 } tgw_outputs;
 
 /* One entry of a thresholded hit list (see tgw_plan_set_hits). */
@@ -299,6 +316,13 @@ tgw_status tgw_scan(tgw_plan* plan, const uint8_t* d_geno, int64_t n_markers, in
  * d_hits == NULL turns the list off.  The autotuner never appends. */
 tgw_status tgw_plan_set_hits(tgw_plan* plan, tgw_hit* d_hits, int64_t capacity, unsigned long long* d_count,
                              float threshold);
+
+/* Per-phenotype top-k words of `panel` (tgw_outputs.topk, n_pheno x k) as
+ * -log10 p (FP64 from |t| at the panel's df, rounded to FP32; NaN for an
+ * empty slot) and absolute marker indices (-1 for an empty slot), both
+ * device arrays of n_pheno x k, row-major.  Asynchronous on `stream`. */
+tgw_status tgw_topk_read(const tgw_panel* panel, const unsigned long long* d_words, int32_t k, float* d_nlog10p,
+                         int64_t* d_marker, void* stream);
 
 /* Synchronizes `stream` and reports device errors / tail overflow of the
  * last tgw_scan on this plan; n_tail receives the number of tail tests. */

@@ -101,7 +101,11 @@ struct OutDev {
   float* nl;
   int64_t ld;
   unsigned long long* best;  // per column: (bits of max -log10 p) << 32 | (0xffffffff - marker)
+  unsigned long long* topk;  // per column: topk_k words (bits of |t|) << 32 | (0xffffffff - marker), decreasing
+  int32_t topk_k;
+  int32_t pad;
 };
+constexpr int kTopKMax = 64;
 
 // thresholded hit list (layout of tgw_hit)
 struct Hit {
@@ -242,6 +246,8 @@ hipError_t launch_bind(const BindArgs& a, hipStream_t s);
 hipError_t launch_tail_reset(TailDev t, hipStream_t s);
 hipError_t launch_tail(TailDev t, const PanelDev* panels, const OutDev* outs, HitDev hits, int64_t m_begin,
                        hipStream_t s);
+hipError_t launch_topk_read(const unsigned long long* words, int64_t n, int k, double df, float* nl, int64_t* marker,
+                            hipStream_t s);
 hipError_t launch_debug_stats(const MarkerStat* ms, int64_t nm, double* shift, double* mean, double* scale,
                               hipStream_t s);
 

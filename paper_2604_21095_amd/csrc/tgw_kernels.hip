@@ -952,6 +952,35 @@ __device__ inline unsigned long long best_pack(float nl, int64_t marker) {
          (unsigned long long)(0xffffffffu - (uint32_t)marker);
 }
 
+// per-column top-k lists: words (bits of |t|) << 32 | (0xffffffff - marker),
+// kept in decreasing order; 0 is an empty slot
+__device__ inline unsigned long long topk_pack(float at, int64_t marker) {
+  return ((unsigned long long)__float_as_uint(at) << 32) | (unsigned long long)(0xffffffffu - (uint32_t)marker);
+}
+
+// Inserts w into the decreasing list s[0..k) that other lanes and workgroups
+// update at the same time.  Every slot only grows (atomicMax), and a value
+// reaches slot i + 1 only by being pushed out of slot i or by starting there
+// after slot i was seen >= it, so s[i] >= s[i + 1] holds at every moment.
+// The search for the first slot below w on plain (possibly stale) reads is
+// therefore safe: every slot it skips is >= w for good.  From there each
+// atomicMax keeps the larger of (slot, w) and w carries the smaller one on,
+// until it lands in an empty slot or drops off the end, below the k-th value.
+__device__ inline void topk_insert(unsigned long long* s, int k, unsigned long long w) {
+  int lo = 0, hi = k;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (__atomic_load_n(s + mid, __ATOMIC_RELAXED) >= w)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  for (int i = lo; i < k && w != 0ull; ++i) {
+    const unsigned long long old = atomicMax(s + i, w);
+    w = old < w ? old : w;
+  }
+}
+
 __device__ inline void append_hit(const HitDev& hits, int64_t marker, int j, int64_t p, float nl, float r) {
   const unsigned long long idx = atomicAdd(hits.count, 1ull);
   if (idx < (unsigned long long)hits.capacity) {
@@ -1153,6 +1182,7 @@ __global__ __launch_bounds__(kRedoThreads) void redo_kernel(RedoArgs a) {
         if (od.t) od.t[o] = (float)t;
         if (od.nl) od.nl[o] = (float)nl;
         if (ok && od.best) atomicMax(od.best + p, best_pack((float)nl, a.m_begin + row));
+        if (ok && od.topk) topk_insert(od.topk + p * od.topk_k, od.topk_k, topk_pack((float)fabs(t), a.m_begin + row));
         if (ok && a.hits.entries && (float)nl >= a.hits.threshold)
           append_hit(a.hits, a.m_begin + row, j, p, (float)nl, (float)r);
       }
@@ -1309,6 +1339,11 @@ __device__ __forceinline__ void finish_block(const float* stage, const GemmArgs&
     odb.t = rebase(od.t);
     odb.nl = rebase(od.nl);
   }
+  // top-k of this lane's column: the list and its current last word (rows
+  // whose word is not above it cannot enter)
+  const bool tk_on = od.topk != nullptr;  // uniform: one panel per column block
+  unsigned long long* tkp = (tk_on && colok) ? od.topk + p * od.topk_k : nullptr;
+  unsigned long long tk_last = tkp ? __atomic_load_n(tkp + od.topk_k - 1, __ATOMIC_RELAXED) : ~0ull;
   if constexpr (!std::is_same<IhPtr, GlobalRows>::value) {
     // the loads above (vector loads: the kernel writes global memory, so
     // they cannot go through the scalar cache) are waited for once here;
@@ -1414,6 +1449,24 @@ __device__ __forceinline__ void finish_block(const float* stage, const GemmArgs&
             const float at = atv[i];
             epilogue_rare(at > kTMax && at != INFINITY, nlv[i], at, rv[i], tab,
                           odb.nl ? at_byte(odb.nl, ob) : (float*)nullptr, row, j, p, a.tail, a.hits, a.m_begin + row);
+          }
+        }
+      }
+    }
+    if (tk_on) {
+      unsigned long long tw[R];
+      uint32_t tkm = 0;
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        tw[i] = topk_pack(atv[i], a.m_begin + a.out_row0 + rowbase + h + 2 * (g + i));
+        tkm |= (okv[i] && atv[i] == atv[i] && tw[i] > tk_last) ? 1u << i : 0u;
+      }
+      if (__builtin_amdgcn_ballot_w64(tkm != 0)) {
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+          if (tkm & (1u << i)) {
+            topk_insert(tkp, od.topk_k, tw[i]);
+            tk_last = __atomic_load_n(tkp + od.topk_k - 1, __ATOMIC_RELAXED);
           }
         }
       }
@@ -2684,6 +2737,30 @@ hipError_t launch_finalize(const MarkerStat* ms, float* wws, float2* invh, int64
   const int64_t total = nm * n_panels;
   hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, ms, wws, invh, nm,
                      n_panels, wscale, redo);
+  return hipGetLastError();
+}
+
+__global__ void topk_read_kernel(const unsigned long long* __restrict__ words, int64_t n, double df,
+                                 float* __restrict__ nl, int64_t* __restrict__ marker) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const unsigned long long w = words[i];
+    if (w == 0ull) {
+      if (nl) nl[i] = __builtin_nanf("");
+      if (marker) marker[i] = -1;
+      continue;
+    }
+    const double at = (double)__uint_as_float((uint32_t)(w >> 32));
+    if (nl) nl[i] = (float)(-ln_p_two_sided(at, df) / M_LN10);
+    if (marker) marker[i] = (int64_t)(0xffffffffu - (uint32_t)w);
+  }
+}
+
+hipError_t launch_topk_read(const unsigned long long* words, int64_t n, int k, double df, float* nl, int64_t* marker,
+                            hipStream_t s) {
+  (void)k;
+  const int64_t blocks = std::min<int64_t>(1024, (n + 255) / 256);
+  hipLaunchKernelGGL(topk_read_kernel, dim3((unsigned)std::max<int64_t>(1, blocks)), dim3(256), 0, s, words, n, df, nl,
+                     marker);
   return hipGetLastError();
 }
 

@@ -703,7 +703,9 @@ tgw_status tgw::check_call(const tgw_plan* pl, const ScanCall& c, bool need_outs
       const bool dense = o.r || o.beta || o.se || o.t || o.nlog10p;
       if (dense && o.ld < pl->panels[j]->P) return fail(TGW_ERR_SHAPE, "outs[j].ld < n_pheno of panel j");
       if (dense && o.ld > kMaxOutLd) return fail(TGW_ERR_SHAPE, "outs[j].ld above 2^22 elements");
-      if (o.best && c.m_end > 0xffffffffll) return fail(TGW_ERR_SHAPE, "best needs marker indices below 2^32");
+      if ((o.best || o.topk) && c.m_end > 0xffffffffll)
+        return fail(TGW_ERR_SHAPE, "best and topk need marker indices below 2^32");
+      if (o.topk && (o.topk_k < 1 || o.topk_k > kTopKMax)) return fail(TGW_ERR_SHAPE, "topk_k must be in [1, 64]");
     }
   }
   return TGW_OK;
@@ -821,7 +823,7 @@ static hipError_t enqueue_bind(tgw_plan* pl, const tgw_outputs* outs, hipStream_
     b.count = std::min(kMaxPanelsPerBind, pl->n_panels - j0);
     for (int i = 0; i < b.count; ++i) {
       const tgw_outputs& o = outs[j0 + i];
-      b.outs[i] = OutDev{o.r, o.beta, o.se, o.t, o.nlog10p, o.ld, o.best};
+      b.outs[i] = OutDev{o.r, o.beta, o.se, o.t, o.nlog10p, o.ld, o.best, o.topk, o.topk ? o.topk_k : 0, 0};
     }
     hipError_t e = launch_bind(b, s);
     if (e != hipSuccess) return e;
@@ -895,6 +897,17 @@ extern "C" tgw_status tgw_scan(tgw_plan* pl, const uint8_t* d_geno, int64_t n_ma
   if (st != TGW_OK) return st;
   if (m_begin == m_end) return TGW_OK;
   HIP_TRY(enqueue_scan(pl, c, (hipStream_t)stream));
+  return TGW_OK;
+  TGW_GUARD_END
+}
+
+extern "C" tgw_status tgw_topk_read(const tgw_panel* panel, const unsigned long long* d_words, int32_t k,
+                                    float* d_nlog10p, int64_t* d_marker, void* stream) {
+  TGW_GUARD_BEGIN
+  if (!panel || !d_words) return fail(TGW_ERR_INVALID_ARG, "NULL argument");
+  if (k < 1 || k > kTopKMax) return fail(TGW_ERR_SHAPE, "k must be in [1, 64]");
+  HIP_TRY(launch_topk_read(d_words, panel->P * (int64_t)k, k, (double)panel->df, d_nlog10p, d_marker,
+                           (hipStream_t)stream));
   return TGW_OK;
   TGW_GUARD_END
 }
@@ -1267,7 +1280,7 @@ extern "C" tgw_status tgw_scan_static(const tgw_panel* const* panels, int32_t n_
   hipStream_t s = (hipStream_t)stream;
   for (int j = 0; j < n_panels; ++j) {
     const tgw_outputs& o = outs[j];
-    sa.outs[j] = OutDev{o.r, o.beta, o.se, o.t, o.nlog10p, o.ld, o.best};
+    sa.outs[j] = OutDev{o.r, o.beta, o.se, o.t, o.nlog10p, o.ld, o.best, o.topk, o.topk ? o.topk_k : 0, 0};
   }
   sa.n_panels = n_panels;
   sa.n_chunks = pl.n_chunks;

@@ -52,7 +52,8 @@ OUTPUT_NAMES = ("r", "beta", "se", "t", "nlog10p")
 class Outputs(ctypes.Structure):
     _fields_ = [("r", ctypes.c_void_p), ("beta", ctypes.c_void_p), ("se", ctypes.c_void_p),
                 ("t", ctypes.c_void_p), ("nlog10p", ctypes.c_void_p), ("ld", ctypes.c_int64),
-                ("best", ctypes.c_void_p)]
+                ("best", ctypes.c_void_p), ("topk", ctypes.c_void_p), ("topk_k", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class Hit(ctypes.Structure):
@@ -124,6 +125,7 @@ _dbg_set_operand = _sig("tgw_debug_set_operand", ctypes.c_int, _vp, _vp, _i64, _
 _dbg_stats = _sig("tgw_debug_marker_stats", ctypes.c_int, _vp, _vp, _i64, _i64, ctypes.c_int, _i64, _i64, _vp, _vp,
                   _vp, _vp)
 _set_allocator = _sig("tgw_set_allocator", ctypes.c_int, _vp, _vp, _vp)
+_topk_read = _sig("tgw_topk_read", ctypes.c_int, _vp, _vp, _i32, _vp, _vp, _vp)
 _scan_static = _sig("tgw_scan_static", ctypes.c_int, ctypes.POINTER(_vp), _i32, _vp, _i64, _i64, ctypes.c_int, _i64,
                     _i64, ctypes.POINTER(Outputs), _i32, _vp, _vp)
 
@@ -319,6 +321,13 @@ def _outs_array(outs: Sequence[Dict[str, torch.Tensor]], panels, n_rows: int):
             if b.dtype != torch.int64 or b.dim() != 1 or not b.is_contiguous() or b.shape[0] < pan.n_pheno:
                 raise ValueError(f"best of panel {j} must be a contiguous int64 vector of n_pheno entries")
             arr[j].best = b.data_ptr()
+        tk = o.get("topk") if o else None
+        if tk is not None:
+            _dev_check(tk)
+            if tk.dtype != torch.int64 or tk.dim() != 2 or not tk.is_contiguous() or tk.shape[0] < pan.n_pheno:
+                raise ValueError(f"topk of panel {j} must be a contiguous int64 (n_pheno, k) matrix")
+            arr[j].topk = tk.data_ptr()
+            arr[j].topk_k = tk.shape[1]
     return arr
 
 
@@ -333,6 +342,22 @@ def unpack_best(best: torch.Tensor):
     nl = (v >> 32).astype("uint32").view("float32")
     marker = (0xFFFFFFFF - (v & 0xFFFFFFFF)).astype("int64")
     marker[v == 0] = -1
+    return nl, marker
+
+
+def make_topk(panel_sizes: Sequence[int], k: int) -> List[torch.Tensor]:
+    """Zeroed per-phenotype top-k lists ((n_pheno, k) int64 words per panel)."""
+    return [torch.zeros((p, k), dtype=torch.int64, device="cuda") for p in panel_sizes]
+
+
+def read_topk(panel: "Panel", words: torch.Tensor, stream=None):
+    """-log10 p (FP64 from |t|, NaN for an empty slot) and marker (-1 empty) of a
+    top-k list, as (n_pheno, k) float32 and int64 device tensors (tgw_topk_read)."""
+    _dev_check(words)
+    nl = torch.empty(words.shape, dtype=torch.float32, device="cuda")
+    marker = torch.empty(words.shape, dtype=torch.int64, device="cuda")
+    _check(_topk_read(panel.handle, _ptr(words), words.shape[1], _ptr(nl), _ptr(marker), _stream(stream)),
+           "tgw_topk_read")
     return nl, marker
 
 
