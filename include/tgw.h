@@ -266,8 +266,9 @@ tgw_status tgw_tile_shape(int32_t idx, int32_t* tile_markers, int32_t* tile_cols
  * records it in a JSON cache keyed by (arch, padded samples, column blocks,
  * panels, precision): $TGW_TUNE_CACHE, default ~/.cache/tgw/tune.json.  A
  * later plan with the same key takes the cached shape without timing.
- * Writes scratch results into `outs`; synchronizes `stream`.  best_ms may be
- * NULL. */
+ * Writes scratch results into `outs` (it scans the markers several times, so
+ * zero best and topk again before the real scan); synchronizes `stream`.
+ * best_ms may be NULL. */
 tgw_status tgw_plan_autotune(tgw_plan* plan, const uint8_t* d_geno, int64_t n_markers, int64_t row_bytes,
                              tgw_geno_code code, int64_t m_begin, int64_t m_end, const tgw_outputs* outs,
                              void* stream, double* best_ms);

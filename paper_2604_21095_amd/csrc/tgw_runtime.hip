@@ -257,9 +257,14 @@ extern "C" const char* tgw_status_string(tgw_status s) {
 extern "C" const char* tgw_last_error(void) { return g_err.c_str(); }
 extern "C" int32_t tgw_abi_version(void) { return TGW_ABI_VERSION; }
 
+static void static_state_init(int dev);  // tgw_scan_static's per-device state
+
 extern "C" tgw_status tgw_init(void) {
   TGW_GUARD_BEGIN
-  return device_info(nullptr, nullptr);
+  int dev = 0;
+  tgw_status st = device_info(&dev, nullptr);
+  if (st == TGW_OK) static_state_init(dev);
+  return st;
   TGW_GUARD_END
 }
 
@@ -1150,6 +1155,8 @@ struct StaticState {
 std::mutex g_static_mu;
 std::map<int, StaticState*> g_static;  // never freed: lives as long as the scratch
 
+// made by tgw_init (or by the first tgw_scan_static on the device), so that
+// later calls find it without allocating
 StaticState* static_state(int dev) {
   std::lock_guard<std::mutex> lk(g_static_mu);
   auto it = g_static.find(dev);
@@ -1162,6 +1169,8 @@ StaticState* static_state(int dev) {
   return s;
 }
 }  // namespace
+
+static void static_state_init(int dev) { (void)static_state(dev); }
 
 extern "C" tgw_status tgw_scan_static(const tgw_panel* const* panels, int32_t n_panels, const uint8_t* d_geno,
                                       int64_t n_markers, int64_t row_bytes, tgw_geno_code code, int64_t m_begin,
