@@ -17,7 +17,7 @@ import numpy as np
 import pytest
 import torch
 
-from synth import pack_codes_np, row_bytes_for
+from synth import dosage8_row_bytes_for, pack_codes_np, row_bytes_for
 from tests.gpu_common import compare, decode_codes, gpu_scan, lib, oracle_scan, say
 from tests.test_gpu_reduced import _check_best, _check_hits
 
@@ -33,21 +33,16 @@ def tgw():
     return t
 
 
-def _workload(n=5000, m=700, seed=404):
-    rng = np.random.default_rng(seed)
-    maf = rng.uniform(0.05, 0.5, m)
-    codes = rng.binomial(2, maf[:, None], size=(m, n)).astype(np.uint8)
-    codes[rng.random((m, n)) < 0.01] = 3
-    G = decode_codes(codes)
-    g_imp = np.where(np.isnan(G), np.nanmean(G, axis=1)[:, None], G)
+def _collinear_covariates(rng, g_imp, n):
+    """Covariates that make markers 1, 4, 7, ... collinear to the ratios RATIOS,
+    marker 40 an exact covariate, plus one ordinary covariate; phenotypes that
+    load on the noise of each collinear covariate."""
     k_c = len(RATIOS)
     Z = rng.standard_normal((n, k_c))
     cols = []
     for k, rho in enumerate(RATIOS):
         g = g_imp[3 * k + 1]  # markers 1, 4, 7, ...: collinear to ratio about rho
-        var = g.var()
-        eps = np.sqrt(rho * var / (1.0 - rho))
-        cols.append(g + eps * Z[:, k])
+        cols.append(g + np.sqrt(rho * g.var() / (1.0 - rho)) * Z[:, k])
     cols.append(g_imp[40].copy())          # marker 40 is a covariate: degenerate
     cols.append(rng.standard_normal(n))    # an ordinary covariate
     C = np.stack(cols, axis=1)
@@ -56,7 +51,18 @@ def _workload(n=5000, m=700, seed=404):
     for k in range(k_c):  # columns 3k .. 3k+2 load on z_k: moderate, strong, extreme
         for i, b in enumerate((0.2, 1.0, 12.0)):
             Y[:, 3 * k + i] += b * Z[:, k]
-    return codes, C, Y.astype(np.float32)
+    return C, Y.astype(np.float32)
+
+
+def _workload(n=5000, m=700, seed=404):
+    rng = np.random.default_rng(seed)
+    maf = rng.uniform(0.05, 0.5, m)
+    codes = rng.binomial(2, maf[:, None], size=(m, n)).astype(np.uint8)
+    codes[rng.random((m, n)) < 0.01] = 3
+    G = decode_codes(codes)
+    g_imp = np.where(np.isnan(G), np.nanmean(G, axis=1)[:, None], G)
+    C, Y = _collinear_covariates(rng, g_imp, n)
+    return codes, C, Y
 
 
 @pytest.mark.parametrize("precision", ["split", "split16", "split8", "fp32"])
@@ -114,3 +120,38 @@ def test_collinear_markers_reduced_two_panels(tgw):
     nl, marker = tgw.unpack_best(best[0])
     # the extreme columns pick their collinear marker, through the FP64 path
     assert np.all(marker[[3 * k + 2 for k in range(len(RATIOS))]] == np.array(planted))
+
+
+@pytest.mark.parametrize("precision", ["split16", "fp32"])
+def test_collinear_markers_dosage8(tgw, precision):
+    """The FP64 path reads 8-bit dosage rows too (q / 127 copies, 255 missing)."""
+    n, m = 5000, 700
+    rng = np.random.default_rng(407)
+    maf = rng.uniform(0.05, 0.5, m)
+    g = rng.binomial(2, maf[:, None], size=(m, n))
+    q = np.clip(127 * g + rng.integers(-30, 31, size=(m, n)), 0, 254).astype(np.uint8)
+    q[rng.random((m, n)) < 0.01] = 255
+    G = np.where(q == 255, np.nan, q / 127.0)
+    g_imp = np.where(np.isnan(G), np.nanmean(G, axis=1)[:, None], G)
+    C, Y = _collinear_covariates(rng, g_imp, n)
+    say(f"case: covariate-collinear markers, 8-bit dosages, {precision}")
+    rows = np.zeros((m, dosage8_row_bytes_for(n)), dtype=np.uint8)
+    rows[:, :n] = q
+    ref = oracle_scan(G, C, Y)
+    res, _, _ = gpu_scan(C, [Y], rows, precision, code=tgw.CODE_DOSAGE8, plan_kw={"block_markers": 512})
+    planted = [3 * k + 1 for k in range(len(RATIOS))]
+    for i in planted:
+        assert np.all(np.isfinite(res[0]["r"][i])), i
+    assert np.all(np.isnan(res[0]["r"][40]))
+    compare(res[0], ref, ref["df"], f"collinear dosage8 {precision} ")
+
+
+def test_collinear_markers_plink_coding(tgw):
+    """The FP64 path decodes PLINK .bed codes (00 / 10 / 11 = 0 / 1 / 2, 01 missing)."""
+    codes, C, Y = _workload(seed=408)
+    n = codes.shape[1]
+    say("case: covariate-collinear markers, PLINK coding, split8")
+    plink = np.array([0, 2, 3, 1], dtype=np.uint8)[codes]  # allele count 0, 1, 2, missing -> .bed code
+    ref = oracle_scan(codes, C, Y)
+    res, _, _ = gpu_scan(C, [Y], pack_codes_np(plink, row_bytes_for(n)), "split8", code=tgw.CODE_PLINK_BED)
+    compare(res[0], ref, ref["df"], "collinear plink split8 ")
