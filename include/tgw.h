@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define TGW_ABI_VERSION 6
+#define TGW_ABI_VERSION 7
 
 typedef enum {
   TGW_OK = 0,
@@ -121,9 +121,11 @@ typedef struct tgw_graph tgw_graph;           /* a captured tgw_scan call     */
  *   t        beta / se = r sqrt(df / (1 - r^2))
  *   nlog10p  -log10 of the two-sided Student-t p-value (df degrees)
  * Degenerate markers (no observed call, monomorphic among observed calls, or
- * ||g_res||^2 <= 1e-4 ||g_c||^2, i.e. the covariates explain 99.99 % of the
- * marker's variance) and degenerate phenotypes (residual norm <= 1e-12 of the
- * centred norm) give NaN in every output.
+ * ||g_res||^2 <= 1e-8 ||g_c||^2 in FP64, i.e. the covariates explain all but
+ * 1e-8 of the marker's variance) and degenerate phenotypes (residual norm
+ * <= 1e-12 of the centred norm) give NaN in every output.  Markers with
+ * ||g_res||^2 < ||g_c||^2 / 2 are finished on an FP64 path (explicit
+ * residualization, FP64 contraction with the stored panel operand).
  *   best     optional reduced output (Methods 2.2, after Eq. 3: the
  *            statistics feed locus ranking and phenotype-level
  *            prioritization): device array of
@@ -206,6 +208,49 @@ typedef struct {
 typedef void* (*tgw_alloc_fn)(size_t bytes, void* stream, void* ctx);
 typedef void (*tgw_free_fn)(void* ptr, void* stream, void* ctx);
 tgw_status tgw_set_allocator(tgw_alloc_fn alloc_fn, tgw_free_fn free_fn, void* ctx);
+
+/* An allocator over one device buffer that the caller owns (for example a
+ * framework tensor): register it with
+ *   tgw_set_allocator(tgw_arena_alloc, tgw_arena_free, arena)
+ * and the handles made afterwards take their device memory (the resident
+ * panel operand and covariate basis of Methods 2.1, the scan workspace, the
+ * temporaries of fit and preparation) from that buffer.
+ *   tgw_arena_create: d_base is a device address aligned to 256 bytes, bytes
+ *     its size (rounded down to a multiple of 256, at least 256).  The
+ *     buffer stays owned by the caller and must outlive the arena; the arena
+ *     never reads or writes it (bookkeeping is on the host).
+ *     TGW_ERR_INVALID_ARG for NULL pointers, TGW_ERR_SHAPE for a misaligned
+ *     or too small buffer.
+ *   tgw_arena_alloc / tgw_arena_free: tgw_alloc_fn / tgw_free_fn with the
+ *     arena as ctx.  Blocks are whole multiples of 256 bytes at 256-byte
+ *     aligned addresses, placed best fit (smallest free range that holds the
+ *     request, lowest address among equals); freed blocks merge with free
+ *     neighbours.  A request the arena cannot hold returns NULL (the tgw call
+ *     then fails with TGW_ERR_OUT_OF_MEMORY) and counts in n_failed; a
+ *     pointer that is not a live block of the arena is ignored and counts in
+ *     n_bad_free.  The stream argument is not used: the library frees only
+ *     memory that no enqueued work still uses.
+ *   tgw_arena_info: occupancy and counters (below).
+ *   tgw_arena_destroy: frees the bookkeeping; TGW_ERR_INVALID_ARG (and the
+ *     arena stays valid) while blocks are in use, i.e. while handles made
+ *     under it are alive.  NULL is a no-op.
+ * Thread-safe (one lock per arena). */
+typedef struct tgw_arena tgw_arena;
+typedef struct {
+  size_t capacity;       /* usable bytes                                  */
+  size_t in_use;         /* bytes in live blocks                          */
+  size_t peak;           /* largest in_use so far                         */
+  size_t largest_free;   /* largest request that would succeed now        */
+  int64_t n_blocks;      /* live blocks                                   */
+  int64_t n_free_ranges; /* free ranges (1 when nothing is in use)        */
+  int64_t n_failed;      /* requests refused                              */
+  int64_t n_bad_free;    /* frees of pointers that were not live blocks   */
+} tgw_arena_stats;
+tgw_status tgw_arena_create(void* d_base, size_t bytes, tgw_arena** out);
+void* tgw_arena_alloc(size_t bytes, void* stream, void* ctx);
+void tgw_arena_free(void* ptr, void* stream, void* ctx);
+tgw_status tgw_arena_info(tgw_arena* arena, tgw_arena_stats* out);
+tgw_status tgw_arena_destroy(tgw_arena* arena);
 
 /* ---- library ---------------------------------------------------------- */
 const char* tgw_status_string(tgw_status s);

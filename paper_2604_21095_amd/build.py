@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libtgw.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("tgw_kernels.hip", "tgw_runtime.hip", "tgw_bed.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("tgw_kernels.hip", "tgw_runtime.hip", "tgw_bed.hip", "tgw_arena.hip")]
 HEADERS = [os.path.join(ROOT, "include", h) for h in ("tgw.h", "tgw_debug.h")]
 
 HIPCC_FLAGS = [

@@ -126,6 +126,10 @@ _dbg_stats = _sig("tgw_debug_marker_stats", ctypes.c_int, _vp, _vp, _i64, _i64, 
                   _vp, _vp)
 _set_allocator = _sig("tgw_set_allocator", ctypes.c_int, _vp, _vp, _vp)
 _topk_read = _sig("tgw_topk_read", ctypes.c_int, _vp, _vp, _i32, _vp, _vp, _vp)
+_arena_create = _sig("tgw_arena_create", ctypes.c_int, _vp, ctypes.c_size_t, _pp)
+_arena_alloc = _sig("tgw_arena_alloc", _vp, ctypes.c_size_t, _vp, _vp)
+_arena_free = _sig("tgw_arena_free", None, _vp, _vp, _vp)
+_arena_destroy = _sig("tgw_arena_destroy", ctypes.c_int, _vp)
 _scan_static = _sig("tgw_scan_static", ctypes.c_int, ctypes.POINTER(_vp), _i32, _vp, _i64, _i64, ctypes.c_int, _i64,
                     _i64, ctypes.POINTER(Outputs), _i32, _vp, _vp)
 
@@ -145,6 +149,68 @@ def set_allocator(alloc_fn=None, free_fn=None, ctx=None):
     """Register C allocator functions (addresses of tgw_alloc_fn / tgw_free_fn) for the
     device memory of handles made afterwards; no arguments restores hipMalloc / hipFree."""
     _check(_set_allocator(alloc_fn, free_fn, ctx), "tgw_set_allocator")
+
+
+class ArenaStats(ctypes.Structure):
+    """tgw_arena_stats."""
+    _fields_ = [("capacity", ctypes.c_size_t), ("in_use", ctypes.c_size_t), ("peak", ctypes.c_size_t),
+                ("largest_free", ctypes.c_size_t), ("n_blocks", _i64), ("n_free_ranges", _i64),
+                ("n_failed", _i64), ("n_bad_free", _i64)]
+
+
+_arena_info = _sig("tgw_arena_info", ctypes.c_int, _vp, ctypes.POINTER(ArenaStats))
+
+
+class Arena:
+    """tgw_arena over one device buffer: `buffer` is a device tensor (its storage is
+    used from its data pointer for nbytes) or, with `nbytes`, a bare device address.
+    The arena keeps a reference to the tensor.  register() makes it the allocator of
+    the handles created afterwards; close() (TgwError while handles made under it are
+    alive) releases the bookkeeping."""
+
+    def __init__(self, buffer, nbytes=None):
+        if nbytes is None:
+            self.buffer = buffer
+            base, nbytes = buffer.data_ptr(), buffer.numel() * buffer.element_size()
+        else:
+            self.buffer, base = None, int(buffer)
+        h = _vp()
+        _check(_arena_create(base, nbytes, ctypes.byref(h)), "tgw_arena_create")
+        self.handle = h
+
+    @property
+    def functions(self):
+        """(alloc_fn, free_fn, ctx) for set_allocator."""
+        return (ctypes.cast(_lib.tgw_arena_alloc, _vp), ctypes.cast(_lib.tgw_arena_free, _vp), self.handle)
+
+    def register(self):
+        set_allocator(*self.functions)
+        return self
+
+    def alloc(self, nbytes) -> int:
+        """One block straight from the arena (0 when it cannot hold it)."""
+        return _arena_alloc(nbytes, None, self.handle) or 0
+
+    def free(self, ptr):
+        _arena_free(ptr, None, self.handle)
+
+    def info(self) -> ArenaStats:
+        st = ArenaStats()
+        _check(_arena_info(self.handle, ctypes.byref(st)), "tgw_arena_info")
+        return st
+
+    def close(self):
+        if self.handle:
+            _check(_arena_destroy(self.handle), "tgw_arena_destroy")
+            self.handle = None
+            self.buffer = None
+
+
+def torch_arena(nbytes: int, device=None) -> Arena:
+    """An arena over one torch allocation of nbytes on the current (or given) device:
+    handles made after .register() take their device memory from torch."""
+    buf = torch.empty(int(nbytes), dtype=torch.uint8, device=device if device is not None else "cuda")
+    return Arena(buf)
 
 
 class TgwError(RuntimeError):

@@ -21,7 +21,7 @@ def test_library_exports_every_declared_symbol(tgw):
     assert "tgw_scan" in syms and "tgw_fit_covariates" in syms and "tgw_prepare_phenotypes" in syms
     missing = [s for s in syms if not hasattr(tgw._lib, s)]
     assert not missing, missing
-    assert tgw.abi_version() == 6
+    assert tgw.abi_version() == 7
 
 
 def test_header_is_plain_c(tmp_path):
