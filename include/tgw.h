@@ -79,9 +79,17 @@ typedef enum {
  *                       operand of TGW_PREC_SPLIT_F16, plus the lo term
  *                       2^12 y~ - hi in FP8 e4m3 (OCP), scaled per column by
  *                       a power of two (E8M0 block scale of the matrix core)
- *                       against the genotype operand rounded to e4m3:
+ *                       against the genotypes centred on the integer c8
+ *                       nearest c (g - c8 exact in e4m3, a missing call
+ *                       mu - c8 rounded to e4m3; the change of centring,
+ *                       (c - c8) times the column's sum of lo terms, is
+ *                       removed with the projection correction; when a
+ *                       panel of the plan has K = 31, c8 = c and the
+ *                       genotype operand is rounded to e4m3 instead):
  *                       relative residual of the panel <= about 2^-16, one
  *                       FP16 pass plus one FP8 pass at twice the FP16 rate.
+ * In every form a marker without missing calls takes gs = 1 and the integer
+ * c = rint(mu) instead (no missing value to carry).
  *                       Runs on the wide tile shapes only (tiles 1 and 6
  *                       select their own; every other index selects tile 0).
  * Covariate QR, phenotype norms and the extreme-tail p-values stay FP64. */

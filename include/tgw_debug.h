@@ -23,7 +23,10 @@ extern "C" {
  * TGW_PREC_SPLIT_F16 and TGW_PREC_SPLIT_F8 the stored columns are scaled by
  * 2^12), where a_m(i) is
  * the re-centred genotype operand described at tgw_scan, times the marker's
- * operand scale gs (see tgw_debug_marker_stats).  d_S is row-major
+ * operand scale gs (see tgw_debug_marker_stats); for TGW_PREC_SPLIT_F8 the
+ * FP8 lo pass takes the genotypes centred on c8 = rint(c) instead when
+ * every panel of the plan has q <= 31 (the scan removes that shift with the
+ * projection correction, this raw contraction keeps it).  d_S is row-major
  * with leading dim lds >= n_pheno.  Used by tests with integer operands. */
 tgw_status tgw_debug_contract(tgw_plan* plan, const uint8_t* d_geno, int64_t n_markers, int64_t row_bytes,
                               tgw_geno_code code, int64_t m_begin, int64_t m_end, float* d_S, int64_t lds,
@@ -43,6 +46,7 @@ tgw_status tgw_debug_set_operand(tgw_panel* panel, const float* d_V, int64_t ldv
  * 2K - U <= 256 (the largest among equals) for which the BF16 rounding error
  * of (K mu - U) / 128 (rounded to FP32 first), divided by K, is smallest.  TGW_PREC_SPLIT_F16 and TGW_PREC_SPLIT_F8: gs = 1,
  * c = rint(512 mu) / 512.  TGW_PREC_FP32: gs = 1, c = rint(64 mu) / 64.
+ * A marker without missing calls, in every form: gs = 1, c = rint(mu).
  * 8-bit dosages: gs = 1, c = rint(mu) in units of 1/127.  Degenerate
  * markers: c = 0, gs = 1.  Test use only. */
 tgw_status tgw_debug_marker_stats(tgw_plan* plan, const uint8_t* d_geno, int64_t n_markers, int64_t row_bytes,

@@ -18,6 +18,9 @@ constexpr int kColBlock = 32;
 constexpr int kBlockBytes = 8192;
 constexpr int kBlockBytes8 = 6144;
 constexpr int kSlots = 32;      // correction slots per (marker, panel): dmu, Q^T g
+// the last slot, free when q <= 31, carries the FP8 lo pass's change of centring
+// (FP16 + FP8 form): (c - c8) per marker against -(sum of lo terms) per column
+constexpr int kLoSlot = kSlots - 1;
 constexpr int kMaxCov = 31;     // K <= 31 so that q = K + 1 <= 32 slots
 constexpr int kMaxPanelsPerBind = 32;
 // Covariate-collinear markers.  The contraction's FP32 rounding error scales
@@ -70,7 +73,7 @@ struct MarkerStat {
   double mu;
   double shift;  // c: mu rounded to U / K (BF16), 1/512 (FP16 forms, FP32: 1/64); 8-bit dosages: to an integer
   float gscale;  // gs: operand units per genotype unit of this marker (K / 128 for BF16, else 1)
-  int32_t pad;
+  float dlo;     // c - c8, c8 the centring of the FP8 lo pass (FP16 + FP8 form), else 0
 };
 
 struct PanelDev {
@@ -185,6 +188,7 @@ struct StatsArgs {
   MarkerStat* mstat;
   uint32_t* redo_count;  // [n_panels]: zeroed by the block's first workgroup
   int32_t n_panels;
+  int32_t lo_int;        // FP16 + FP8 form: the FP8 lo pass centres on the integer c8 = rint(c)
 };
 
 // markers left to the FP64 kernel, per panel: rows (within the marker block)
@@ -240,7 +244,7 @@ hipError_t launch_set_operand(const float* V, int64_t ldv, int64_t n, int64_t n_
 hipError_t launch_table(float4* table, double df, hipStream_t s);
 hipError_t launch_stats(const StatsArgs& a, hipStream_t s);
 hipError_t launch_finalize(const MarkerStat* ms, float* wws, float2* invh, int64_t nm, int n_panels, float wscale,
-                           RedoDev redo, hipStream_t s);
+                           int lo_slot, RedoDev redo, hipStream_t s);
 hipError_t launch_redo(const RedoArgs& a, int grid, hipStream_t s);
 hipError_t launch_bind(const BindArgs& a, hipStream_t s);
 hipError_t launch_tail_reset(TailDev t, hipStream_t s);

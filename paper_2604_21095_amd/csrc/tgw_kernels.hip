@@ -196,8 +196,11 @@ __device__ inline void split_parts(int prec, double v, uint32_t* hb, uint32_t* l
   }
 }
 
+// stored: the value the operand now holds (in 2^12 units for the FP16
+// forms); lo: its FP8 lo term alone (FP16 + FP8 form; 0 otherwise)
 __device__ inline void store_operand(void* op, int prec, int64_t col, int64_t i, int n_chunks, double v,
-                                     double* stored, int lsh = 0) {
+                                     double* stored, int lsh = 0, double* lo = nullptr) {
+  if (lo) *lo = 0.0;
   if (prec == kSplit8) {
     const double vs = v * (double)kF16Scale;
     const uint32_t hb = f16_bits_rn((float)vs);
@@ -205,7 +208,9 @@ __device__ inline void store_operand(void* op, int prec, int64_t col, int64_t i,
     const uint32_t qb = e4m3_bits_rne(ldexp(vs - hi, lsh));
     ((uint16_t*)op)[operand_index_split(col, i, n_chunks, 0, kBlockBytes8 / 2)] = (uint16_t)hb;
     ((uint8_t*)op)[operand_index_lo8(col, i, n_chunks)] = (uint8_t)qb;
-    *stored = hi + ldexp(e4m3_value(qb), -lsh);
+    const double lv = ldexp(e4m3_value(qb), -lsh);
+    *stored = hi + lv;
+    if (lo) *lo = lv;
   } else if (prec == kSplit16 || prec == kSplit) {
     uint32_t hb, lb;
     split_parts(prec, v, &hb, &lb);
@@ -630,19 +635,24 @@ __global__ __launch_bounds__(kPrepThreads) void prep_kernel(const void* __restri
   }
 
   // pass 4: y~ = y_res / s_p into the operand; accumulate what the stored
-  // (rounded) operand actually holds: Q^T y_op, sum (slot QS), norm^2 (QS + 1)
+  // (rounded) operand actually holds: Q^T y_op, sum (slot QS), norm^2 (QS + 1),
+  // and (FP16 + FP8 form) the sum of the FP8 lo terms alone
 #pragma unroll
   for (int c = 0; c < CPW; ++c)
 #pragma unroll
     for (int k = 0; k < QS + 2; ++k) acc[c][k] = 0.0;
+  double lsum[CPW];
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) lsum[c] = 0.0;
   for (int64_t i = tid; i < n; i += kPrepThreads) {
     double qv[QS];
     load_q(i, qv);
 #pragma unroll
     for (int c = 0; c < CPW; ++c) {
       if (p0 + c >= P) continue;
-      double st;
-      store_operand(yop, prec, p0 + c, i, n_chunks, yres(c, i, qv) * inv[c], &st, lsh[c]);
+      double st, lo;
+      store_operand(yop, prec, p0 + c, i, n_chunks, yres(c, i, qv) * inv[c], &st, lsh[c], &lo);
+      lsum[c] += lo;
       acc[c][QS] += st;
       acc[c][QS + 1] += st * st;
 #pragma unroll
@@ -651,6 +661,11 @@ __global__ __launch_bounds__(kPrepThreads) void prep_kernel(const void* __restri
     }
   }
   block_sum_vec<kPrepThreads, NV>(&acc[0][0], sh);
+  // FP16 + FP8 form with q <= 31: the last correction slot takes minus the
+  // column's sum of lo terms (a plan whose markers centre their FP8 pass on
+  // c8 = rint(c) puts c - c8 against it)
+  const bool lo_slot = prec == kSplit8 && q <= kLoSlot;
+  if (lo_slot) block_sum_vec<kPrepThreads, CPW>(lsum, sh);
 #pragma unroll
   for (int c = 0; c < CPW; ++c) {
     const int64_t p = p0 + c;
@@ -669,6 +684,7 @@ __global__ __launch_bounds__(kPrepThreads) void prep_kernel(const void* __restri
 #pragma unroll
       for (int k = 1; k < QS; ++k)
         if (tid == k && k < q) v = (float)(-acc[c][k]);
+      if (lo_slot && tid == kLoSlot) v = (float)(-lsum[c]);
       cw[p * kSlots + tid] = v;
     }
   }
@@ -748,7 +764,7 @@ __device__ void stats_dosage8(const StatsArgs& a, int64_t m, int lane) {
   st.mu = mu;
   st.shift = c;
   st.gscale = 1.0f;
-  st.pad = 0;
+  st.dlo = 0.0f;
   st.gc2 = n_obs > 0 ? (double)num128 / (double)n_obs : 0.0;
   st.dmu = (float)(mu - c);
   const uint32_t nc = f16_bits_rn((float)(-1024.0 - c));
@@ -823,8 +839,17 @@ __global__ __launch_bounds__(256) void stats_kernel(StatsArgs a) {
   // simple fraction such as 1/2 or 1), typically below 2^-24, against up
   // to 2^-16 for the nearest multiple of 1/64.  The 256 candidates are
   // spread over the wave's lanes.
+  // A marker without missing calls carries no missing value: every form
+  // takes gs = 1 and the integer c = rint(mu), so that its operand holds
+  // small integers, whose few changing bits cost the matrix cores less
+  // power than fractional values (the contraction's clock is power-bound).
+  const bool whole = ok && nmiss == 0;
   double c = 0.0, gs = 1.0, vmiss = mu, vg[3] = {0.0, 1.0, 2.0};  // degenerate: not re-centred
-  if (ok && a.prec == kSplit) {
+  if (whole) {
+    c = rint(mu);
+    vmiss = mu - c;
+    for (int g = 0; g < 3; ++g) vg[g] = (double)g - c;
+  } else if (ok && a.prec == kSplit) {
     double best = INFINITY;
     int bk = 0;
     for (int K = 256 - lane; K >= 1; K -= 64) {
@@ -863,7 +888,14 @@ __global__ __launch_bounds__(256) void stats_kernel(StatsArgs a) {
   st.mu = mu;
   st.shift = c;
   st.gscale = (float)gs;
-  st.pad = 0;
+  // the FP8 lo pass of the FP16 + FP8 form may centre on the integer c8 =
+  // rint(c): its calls' values g - c8 are then exact in e4m3 and, being
+  // small integers, cheaper in matrix-core power; a missing call's mu - c8
+  // rounds to e4m3, an error that the lo term of y~ (about 2^-12 of y~)
+  // keeps below about 2^-17 of a genotype unit.  The shift (c - c8) times
+  // the column's sum of lo terms leaves through the last correction slot.
+  const double c8 = (a.prec == kSplit8 && a.lo_int) ? rint(c) : c;
+  st.dlo = (float)(c - c8);  // a multiple of 1/512 in [-1/2, 1/2]: exact
   st.gc2 = n_obs > 0 ? (double)num / (double)n_obs : 0.0;
   st.dmu = (float)vmiss;
   // operand value of each 2-bit code, in the coding scheme's code order
@@ -880,7 +912,7 @@ __global__ __launch_bounds__(256) void stats_kernel(StatsArgs a) {
       const uint32_t b = a.prec == kSplit ? bf16_bits_rne((float)val[k]) : f16_bits_rn((float)val[k]);
       lo8 |= (b & 0xffu) << (8 * k);
       hi8 |= (b >> 8) << (8 * k);
-      f8 |= e4m3_bits_rne(val[k]) << (8 * k);  // the FP8 lo pass sees g - c rounded to e4m3
+      f8 |= e4m3_bits_rne(val[k] + (c - c8)) << (8 * k);  // g - c8, or mu - c8, rounded to e4m3
     }
     lut = make_uint4(lo8, hi8, f8, 0u);
   } else {
@@ -908,7 +940,8 @@ __global__ void debug_stats_kernel(const MarkerStat* ms, int64_t nm, double* shi
 // kernel then writes NaN rows and no reduced outputs) and go to the FP64
 // list of their panel.
 __global__ void finalize_kernel(const MarkerStat* __restrict__ ms, float* __restrict__ wws,
-                                float2* __restrict__ invh, int64_t nm, int n_panels, float wscale, RedoDev redo) {
+                                float2* __restrict__ invh, int64_t nm, int n_panels, float wscale, int lo_slot,
+                                RedoDev redo) {
   const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (idx >= nm * n_panels) return;
   const int64_t m = idx / n_panels;
@@ -931,6 +964,7 @@ __global__ void finalize_kernel(const MarkerStat* __restrict__ ms, float* __rest
   const double ih = 1.0 / sqrt(h2);
   invh[idx] = ok ? make_float2((float)(ih * igs), (float)ih) : make_float2(__builtin_nanf(""), __builtin_nanf(""));
   ws[0] = st.dmu;
+  if (lo_slot) ws[kLoSlot] = st.dlo;  // the slot's Q^T g is 0 (q <= 31 in every panel of the plan)
 }
 
 // ---------------------------------------------------------------------------
@@ -2732,11 +2766,10 @@ hipError_t launch_stats(const StatsArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_finalize(const MarkerStat* ms, float* wws, float2* invh, int64_t nm, int n_panels, float wscale,
-                           RedoDev redo,
-                           hipStream_t s) {
+                           int lo_slot, RedoDev redo, hipStream_t s) {
   const int64_t total = nm * n_panels;
   hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, ms, wws, invh, nm,
-                     n_panels, wscale, redo);
+                     n_panels, wscale, lo_slot, redo);
   return hipGetLastError();
 }
 

@@ -225,6 +225,9 @@ struct tgw_plan {
   int n_cb_w = 0;     // column blocks of the Q^T g contraction
   // 8-bit dosage rows (the FP32 and FP16 split forms): own tile choice and grids
   int tile8 = 2;
+  // FP16 + FP8 form with q <= 31 in every panel: the FP8 lo pass centres on
+  // the integer rint(c), its shift removed through the last correction slot
+  bool lo_int = false;
   std::vector<int> grid_main8;
   int grid_w8 = 0;
   bool profile = false;
@@ -468,6 +471,15 @@ extern "C" tgw_status tgw_debug_set_operand(tgw_panel* p, const float* d_V, int6
 // ---------------------------------------------------------------------------
 // plans
 // ---------------------------------------------------------------------------
+// the FP8 lo pass's integer centring needs the last correction slot free in
+// every panel (the markers' operand tables are shared by the plan's panels)
+static bool lo_int_for(int prec, const tgw_panel* const* panels, int n_panels) {
+  if (prec != kSplit8) return false;
+  for (int j = 0; j < n_panels; ++j)
+    if (panels[j]->cov->q > kLoSlot) return false;
+  return true;
+}
+
 extern "C" void tgw_plan_free(tgw_plan* pl) {
   if (!pl) return;
   for (auto& ev : pl->prof_events) {
@@ -620,6 +632,7 @@ extern "C" tgw_status tgw_plan_create(const tgw_panel* const* panels, int32_t n_
   }
   pl->n_cb = (int)cbm.size();
   pl->n_cb_w = (int)cbw.size();
+  pl->lo_int = lo_int_for(pl->prec, panels, n_panels);
   const int64_t per_marker = (int64_t)sizeof(uint4) + sizeof(MarkerStat) + (int64_t)n_panels * (kSlots + 3) * 4;
   int64_t MB = o.block_markers;
   if (MB == 0) MB = std::max<int64_t>(4096, std::min<int64_t>(1 << 20, (2ll << 30) / per_marker));
@@ -753,6 +766,7 @@ static hipError_t enqueue_block_stats(tgw_plan* pl, const ScanCall& c, int64_t m
   sa.mstat = pl->mstat;
   sa.redo_count = pl->redo_count;
   sa.n_panels = pl->n_panels;
+  sa.lo_int = pl->lo_int ? 1 : 0;
   hipError_t e = launch_stats(sa, s);
   if (e != hipSuccess) return e;
   GemmArgs a = base_args(pl, c, m0, nm);
@@ -767,7 +781,7 @@ static hipError_t enqueue_block_stats(tgw_plan* pl, const ScanCall& c, int64_t m
   e = launch_gemm(wgemm_tile(), wprec(pl->prec), pl->w_mode, a, g8 ? pl->grid_w8 : pl->grid_w, s, g8);
   if (e != hipSuccess) return e;
   return launch_finalize(pl->mstat, pl->wws, pl->invh, nm, pl->n_panels,
-                         f16_scaled(pl->prec) ? 1.0f / kF16Scale : 1.0f,
+                         f16_scaled(pl->prec) ? 1.0f / kF16Scale : 1.0f, pl->lo_int ? 1 : 0,
                          RedoDev{pl->redo_entries, pl->redo_count, pl->MB}, s);
 }
 
@@ -1271,6 +1285,7 @@ extern "C" tgw_status tgw_scan_static(const tgw_panel* const* panels, int32_t n_
   pl.tail_cap = kStaticTail;
   pl.hits = HitDev{};
   pl.w_mode = hl ? kRawHL : kRaw;
+  pl.lo_int = lo_int_for(prec, panels, n_panels);
   pl.profile = false;
   pl.tile = tile >= 0 ? tile : 0;
   pl.tile8 = tile >= 0 ? tile : 2;
@@ -1341,6 +1356,7 @@ extern "C" tgw_status tgw_debug_contract(tgw_plan* pl, const uint8_t* d_geno, in
     sa.prec = pl->prec;
     sa.mlut = pl->mlut;
     sa.mstat = pl->mstat;
+    sa.lo_int = pl->lo_int ? 1 : 0;
     HIP_TRY(launch_stats(sa, s));
     GemmArgs a = base_args(pl, c, m0, nm);
     const bool g8 = code == TGW_CODE_DOSAGE8;
@@ -1378,6 +1394,7 @@ extern "C" tgw_status tgw_debug_marker_stats(tgw_plan* pl, const uint8_t* d_geno
     sa.prec = pl->prec;
     sa.mlut = pl->mlut;
     sa.mstat = pl->mstat;
+    sa.lo_int = pl->lo_int ? 1 : 0;
     HIP_TRY(launch_stats(sa, s));
     HIP_TRY(launch_debug_stats(pl->mstat, nm, d_shift ? d_shift + (m0 - m_begin) : nullptr,
                                d_mean ? d_mean + (m0 - m_begin) : nullptr,

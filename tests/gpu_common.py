@@ -141,14 +141,27 @@ def bf16_round(x: np.ndarray) -> np.ndarray:
 GRID = {"split16": 512, "split8": 512, "fp32": 64}
 
 
-def recentre(mu: np.ndarray, ok: np.ndarray, precision: str):
+def recentre(mu: np.ndarray, ok: np.ndarray, precision: str, complete=None):
     """Per-marker re-centring of the genotype operand as tgw_debug_marker_stats
     documents it: returns (c, gs, obs, miss) with obs[m, g] the exact operand
     value gs (g - c) of a call g = 0, 1, 2 and miss[m] the unrounded missing
     value gs (mu - c).  BF16 split: gs = K / 128, c = U / K over K = 1..256
     with U = rint(K mu) <= 256 and 2K - U <= 256, the K whose missing value
     rounds to BF16 with the least error / K (ties: larger K).  Degenerate
-    markers (ok False): c = 0, gs = 1, missing value mu."""
+    markers (ok False): c = 0, gs = 1, missing value mu.  Markers without
+    missing calls (complete True, ok True), every form: c = rint(mu), gs = 1."""
+    c, gs, obs, miss = _recentre_partial(mu, ok, precision)
+    if complete is not None:
+        whole = np.asarray(complete, dtype=bool) & np.asarray(ok, dtype=bool)
+        ci = np.rint(np.asarray(mu, dtype=np.float64))
+        c = np.where(whole, ci, c)
+        gs = np.where(whole, 1.0, gs)
+        obs = np.where(whole[:, None], np.arange(3)[None, :] - ci[:, None], obs)
+        miss = np.where(whole, mu - ci, miss)
+    return c, gs, obs, miss
+
+
+def _recentre_partial(mu, ok, precision):
     mu = np.asarray(mu, dtype=np.float64)
     m = mu.shape[0]
     c = np.zeros(m)

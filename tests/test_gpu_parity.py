@@ -51,8 +51,10 @@ def test_contraction_exact_integers(tgw, precision, n, m, p, tile):
     np.testing.assert_array_equal(mean, codes.mean(axis=1))
     ok = np.ones(m, dtype=bool)
     ok[5] = False  # degenerate (monomorphic) markers are not re-centred
-    want_shift, want_gs, obs_val, _ = recentre(codes.mean(axis=1), ok, precision)
+    # no missing calls: every marker takes the integer centring rint(mu)
+    want_shift, want_gs, obs_val, _ = recentre(codes.mean(axis=1), ok, precision, complete=np.ones(m, dtype=bool))
     np.testing.assert_array_equal(shift, want_shift)
+    assert np.all(shift == np.rint(shift))
     np.testing.assert_array_equal(gs, want_gs)
     if precision in F16_FORMS:
         S = S / tgw.F16_SCALE  # the FP16 forms store 2^12 times the operand
@@ -84,7 +86,7 @@ def test_contraction_missing_value(tgw, precision):
     mu = np.where(obs, codes, 0).sum(1) / obs.sum(1)
     np.testing.assert_allclose(mean, mu, rtol=1e-15)
     ok = np.array([len(set(row[row < 3].tolist())) > 1 for row in codes])
-    want_shift, want_gs, obs_val, vm = recentre(mean, ok, precision)
+    want_shift, want_gs, obs_val, vm = recentre(mean, ok, precision, complete=obs.all(axis=1))
     np.testing.assert_array_equal(shift, want_shift)
     np.testing.assert_array_equal(gs, want_gs)
     if precision == "split":
@@ -111,19 +113,25 @@ def _e4m3(x: np.ndarray) -> np.ndarray:
         torch.float64).numpy()
 
 
-def test_contraction_fp8_lo_term(tgw):
+@pytest.mark.parametrize("k", [0, 31])
+def test_contraction_fp8_lo_term(tgw, k):
     """FP16 hi + FP8 lo form on non-integer operands: the contraction equals
     A16 @ hi + A8 @ lo8 * 2^-s, with hi = fp16(2^12 v), lo8 = e4m3((2^12 v - hi) 2^s)
-    for the column's shift s, A16 the re-centred genotypes (exact in FP16) and
-    A8 = e4m3(A16).  The lo term is ~2^-12 of the total, so a wrong sample
-    order, decode or scale in the FP8 pass fails the 1e-6 bound."""
-    say("case: FP8 lo term of the FP16 hi + FP8 lo contraction")
+    for the column's shift s, A16 the re-centred genotypes g - c (exact in
+    FP16) and A8 the genotypes centred on c8: g - c8, missing calls
+    e4m3(mu - c8).  c8 = rint(c) (A8 exact for calls) when every panel of the
+    plan has q <= 31, whose last correction slot then takes the shift; c8 = c
+    at K = 31 (q = 32).  The lo term is ~2^-12 of the total, so a wrong
+    sample order, decode, centring or scale in the FP8 pass fails the 1e-6
+    bound."""
+    say(f"case: FP8 lo term of the FP16 hi + FP8 lo contraction, K = {k}")
     rng = np.random.default_rng(61)
     n, m, p = 1000, 700, 70
     codes = rng.integers(0, 3, size=(m, n)).astype(np.uint8)
     codes[rng.random((m, n)) < 0.03] = 3
     V = (rng.standard_normal((n, p)) * np.exp(rng.uniform(-3, 3, size=p))[None, :] / np.sqrt(n)).astype(np.float32)
-    cov = tgw.fit_covariates(None, n_samples=n)
+    C = torch.from_numpy(rng.standard_normal((n, k))).cuda() if k else None
+    cov = tgw.fit_covariates(C, n_samples=n)
     panel = tgw.prepare_phenotypes(cov, torch.randn(n, p, dtype=torch.float32, device="cuda"), "split8")
     panel.debug_set_operand(torch.from_numpy(V).cuda())
     plan = tgw.Plan([panel])
@@ -133,7 +141,8 @@ def test_contraction_fp8_lo_term(tgw):
     obs = codes < 3
     mu = np.where(obs, codes, 0).sum(1) / obs.sum(1)
     A16 = np.where(obs, codes - shift[:, None], (mu - shift)[:, None].astype(np.float16).astype(np.float64))
-    A8 = _e4m3(np.where(obs, codes - shift[:, None], (mu - shift)[:, None]))
+    c8 = np.rint(shift) if k < 31 else shift  # the FP8 pass's centring
+    A8 = _e4m3(np.where(obs, codes - c8[:, None], (mu - c8)[:, None]))
     vs = V.astype(np.float64) * tgw.F16_SCALE
     hi = vs.astype(np.float16).astype(np.float64)
     lo = vs - hi
@@ -494,6 +503,71 @@ def test_cfg5_batching_form_sampled(tgw, precision):
 
 
 @pytest.mark.parametrize("precision", PRECS)
+def test_markers_without_missing_calls(tgw, precision):
+    """Markers with no missing call are centred on the integer rint(mu) in every
+    form (they carry no missing value); beside markers with missing calls, in
+    the same blocks, both kinds meet the oracle."""
+    spec = cohort_spec("cfg1", n_markers=1500)
+    say(f"case: markers without missing calls {precision}")
+    codes, _, C, Y = cohort_arrays(spec, np.arange(spec.n_markers))
+    rng = np.random.default_rng(71)
+    whole = rng.random(codes.shape[0]) < 0.5
+    codes = np.where(whole[:, None] & (codes == 3), rng.integers(0, 3, size=codes.shape, dtype=np.uint8), codes)
+    packed = pack_codes_np(codes, row_bytes_for(spec.n_samples))
+    res, _, panels = gpu_scan(C, [Y], packed, precision)
+    ref = oracle_scan(codes, C, Y)
+    compare(res[0], ref, ref["df"], f"without missing calls {precision} ")
+    plan = tgw.Plan(panels)
+    shift, mean, gs = [x.cpu().numpy() for x in plan.debug_marker_stats(torch.from_numpy(packed).cuda())]
+    obs = codes < 3
+    ok = ref["gc2"] > 0  # not monomorphic among observed calls
+    want_shift, want_gs, _, _ = recentre(mean, ok, precision, complete=obs.all(axis=1))
+    np.testing.assert_array_equal(shift, want_shift)
+    np.testing.assert_array_equal(gs, want_gs)
+    assert np.all(shift[whole & ok] == np.rint(mean[whole & ok]))
+
+
+def _e4m3_lo_sums(Yt: np.ndarray, scale: float) -> np.ndarray:
+    """Per column: the sum of the FP8 lo terms that the FP16 + FP8 form stores
+    for the unit columns Yt (in units of 1 / scale), computed here from the
+    form's definition (hi = fp16(scale y), lo = e4m3((scale y - hi) 2^s) 2^-s)."""
+    vs = Yt * scale
+    hi = vs.astype(np.float16).astype(np.float64)
+    lo = vs - hi
+    mx = np.abs(lo).max(axis=0)
+    sh = np.where(mx > 0, np.floor(np.log2(448.0 / np.where(mx > 0, mx, 1.0))), 0.0)
+    return (_e4m3(lo * 2.0 ** sh[None, :]) * 2.0 ** -sh[None, :]).sum(axis=0)
+
+
+def test_fp8_lo_centring_shift_removed(tgw):
+    """The FP8 pass of the FP16 + FP8 form runs on g - c8 with c8 = rint(c), which
+    shifts the contraction by (c - c8) L_p, L_p the column's sum of FP8 lo
+    terms; the last projection-correction slot removes it.  Two-valued phenotypes without covariates
+    give every sample of a column one of two rounding residuals, so L_p is
+    large: left in, the shift would move r by many times the tolerance
+    (checked here from the form's definition); the scan meets the oracle."""
+    say("case: FP8 lo centring shift, two-valued phenotypes, K = 0")
+    rng = np.random.default_rng(72)
+    n, m = 8001, 900
+    maf = rng.uniform(0.05, 0.5, m)
+    codes = rng.binomial(2, maf[:, None], size=(m, n)).astype(np.uint8)
+    codes[rng.random((m, n)) < 0.02] = 3
+    Y = np.stack([(rng.random(n) < f).astype(np.float32) for f in (0.1, 0.3, 0.5, 0.7, 0.9)] +
+                 [rng.standard_normal(n).astype(np.float32)], axis=1)
+    ref = oracle_scan(codes, None, Y)
+    Yt = oracle.prepare_panel(Y.astype(np.float64), oracle.covariate_basis(np.zeros((n, 0))))[0]
+    L = _e4m3_lo_sums(Yt, tgw.F16_SCALE)
+    G = decode_codes(codes)
+    mu = np.nanmean(G, axis=1)
+    c = np.rint(512.0 * mu) / 512.0
+    shift_r = np.abs(np.outer(c - np.rint(c), L)) / tgw.F16_SCALE / ref["h"][:, None]
+    say(f"column lo sums {np.array2string(L, precision=3)}; uncorrected shift of r up to {shift_r.max():.3g}")
+    assert shift_r.max() > 10 * R_TOL
+    res, _, _ = gpu_scan(None, [Y], pack_codes_np(codes, row_bytes_for(n)), "split8")
+    compare(res[0], ref, ref["df"], "lo centring shift ")
+
+
+@pytest.mark.parametrize("precision", PRECS)
 def test_phenotype_dependent_missingness(tgw, precision):
     """Missing calls concentrated where one phenotype is high (up to 40 %): the
     imputed value's operand rounding is then aligned with that phenotype, the
@@ -519,7 +593,7 @@ def test_phenotype_dependent_missingness(tgw, precision):
         G = decode_codes(codes)
         miss = np.isnan(G)
         mu = np.nanmean(G, axis=1)
-        _, gs, _, vm = recentre(mu, np.ones(m, dtype=bool), precision)
+        _, gs, _, vm = recentre(mu, np.ones(m, dtype=bool), precision, complete=~miss.any(axis=1))
         e_m = np.abs(bf16_round(vm) - vm) / gs
         say(f"BF16 missing-value error per genotype unit: max {e_m.max():.3g} (nearest 1/64: <= {2.0 ** -16:.3g})")
         Yt = oracle.prepare_panel(Y.astype(np.float64), oracle.covariate_basis(C))[0]
