@@ -362,6 +362,44 @@ def dosage_run(args, tgw, torch):
     return out
 
 
+def complete_calls_run(args, tgw, torch, tile, geno, Cd, Yd):
+    """Markers without missing calls take the integer centring c = rint(mu),
+    whose operand values cost the matrix cores less power: the headline
+    precision and tile over args.complete_markers markers of the workload's
+    cohort, once as generated (missing calls at the workload's rate: the
+    headline rows) and once regenerated without missing calls, reduced
+    outputs (best test), main kernel timed with HIP events (one warm-up and
+    two timed scans each, alternating)."""
+    from synth import cohort_spec, packed_rows_torch, row_bytes_for
+    spec0 = cohort_spec(args.workload)
+    M = min(args.complete_markers, geno.shape[0])
+    spec = spec0.__class__(**{**spec0.__dict__, "n_markers": M, "miss_rate": 0.0})
+    whole = torch.empty((M, row_bytes_for(spec.n_samples)), dtype=torch.uint8, device="cuda")
+    packed_rows_torch(spec, 0, M, "cuda", out=whole, chunk=32768)
+    torch.cuda.synchronize()
+    P = Yd.shape[1]
+    best = tgw.make_best([P])[0]
+    plan = tgw.Plan([tgw.prepare_phenotypes(tgw.fit_covariates(Cd), Yd, args.precision)], tile=tile)
+    times = {"missing": [], "complete": []}
+    for rep in range(3):
+        for name, g in (("missing", geno), ("complete", whole)):
+            plan.profile(True)
+            plan.scan(g, [{"best": best}], 0, M)
+            plan.check()
+            ms, n = plan.profile_read()
+            plan.profile(False)
+            if rep:
+                times[name].append(ms / max(1, n))
+    a, b = min(times["missing"]), min(times["complete"])
+    out = {"workload": f"{args.workload} cohort, M={M}, {args.precision}, tile {tile}, reduced outputs (best test)",
+           "main_kernel_ms_with_missing_calls": a, "main_kernel_ms_without_missing_calls": b,
+           "speedup": a / b}
+    log(f"complete calls: main kernel {a:.2f} ms with 1% missing calls, {b:.2f} ms without ({a / b:.3f}x)")
+    del whole, plan, best
+    torch.cuda.empty_cache()
+    return out
+
+
 def bed_stream_run(args, tgw, torch, tile):
     """The headline precision over args.bed_markers markers of the workload's
     cohort streamed from a PLINK 1 .bed file (written to a temporary directory,
@@ -451,6 +489,8 @@ def main():
                     help="markers of the 8-bit dosage run beside the headline (0 = skip)")
     ap.add_argument("--bed-markers", type=int, default=262144,
                     help="markers of the .bed streaming run beside the headline (0 = skip)")
+    ap.add_argument("--complete-markers", type=int, default=262144,
+                    help="markers of the run with and without missing calls beside the headline (0 = skip)")
     ap.add_argument("--bed-block", type=int, default=32768)
     ap.add_argument("--bed-threads", type=int, default=8)
     ap.add_argument("--no-panel-scale", action="store_true",
@@ -602,6 +642,11 @@ def main():
                         "tile": planb.info()["tile"]}
         log(f"{prec}: {dtb * 1e3:.1f} ms/step, {tests / dtb:.3e} tests/s, main kernel {msb:.2f} ms")
 
+    # ---------------------------------------------------------------- markers without missing calls
+    complete = None
+    if args.complete_markers > 0 and not args.markers:
+        complete = complete_calls_run(args, tgw, torch, info["tile"], geno, Cds[0], Yds[0])
+
     # ---------------------------------------------------------------- streamed from a .bed file
     bed_stream = None
     if args.bed_markers > 0 and not args.markers:
@@ -692,6 +737,7 @@ def main():
         "panel_scale": panel_scale,
         "bed_stream": bed_stream,
         "dosage8_scan": dosage,
+        "complete_calls": complete,
         "batching": batching,
         "outputs": ("dense r, beta, se, t, -log10 p" if not reduced else
                     f"reduced: per-phenotype best test" + (f" + top {args.topk}" if args.topk > 0 else "")

@@ -567,6 +567,31 @@ def test_fp8_lo_centring_shift_removed(tgw):
     compare(res[0], ref, ref["df"], "lo centring shift ")
 
 
+def test_fp8_lo_centring_off_with_a_k31_panel(tgw):
+    """A plan holding a K = 31 panel (q = 32: no free correction slot) runs the
+    FP8 pass of all its panels on c8 = c; each panel still meets the oracle,
+    and the small-K panel agrees with its own plan (which centres on rint(c))
+    to well inside the tolerance."""
+    spec = cohort_spec("cfg1", n_markers=1500)
+    say("case: FP16 + FP8 plan with a K = 31 panel beside a K = 4 panel")
+    codes, packed, C, Y = cohort_arrays(spec, np.arange(spec.n_markers))
+    rng = np.random.default_rng(73)
+    n = spec.n_samples
+    C31 = rng.standard_normal((n, 31))
+    Y31 = (rng.standard_normal((n, 9)) + C31[:, :3] @ rng.standard_normal((3, 9))).astype(np.float32)
+    res, _, _ = gpu_scan(C, [Y], packed, "split8")
+    covs = [tgw.fit_covariates(torch.from_numpy(c).cuda()) for c in (C, C31)]
+    panels = [tgw.prepare_phenotypes(cv, torch.from_numpy(y).cuda(), "split8") for cv, y in zip(covs, (Y, Y31))]
+    outs = tgw.scan(tgw.Plan(panels), torch.from_numpy(packed).cuda())
+    got = [{k: v.cpu().numpy() for k, v in o.items()} for o in outs]
+    for j, (c, y) in enumerate(((C, Y), (C31, Y31))):
+        ref = oracle_scan(codes, c, y)
+        compare(got[j], ref, ref["df"], f"K = {c.shape[1]} panel of the mixed plan ")
+    dr = np.nanmax(np.abs(got[0]["r"] - res[0]["r"]))
+    say(f"K = 4 panel, mixed plan vs its own plan: max |dr| {dr:.3g}")
+    assert dr < 2e-6
+
+
 @pytest.mark.parametrize("precision", PRECS)
 def test_phenotype_dependent_missingness(tgw, precision):
     """Missing calls concentrated where one phenotype is high (up to 40 %): the
