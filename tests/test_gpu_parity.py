@@ -223,11 +223,14 @@ def test_edge_cases(tgw, precision):
     compare(res0[0], ref0, ref0["df"], f"edge K=0 {precision} ")
 
 
-@pytest.mark.parametrize("precision", PRECS)
-def test_plink_coding_and_k31(tgw, precision):
+@pytest.mark.parametrize("precision,k", [(p, 31) for p in PRECS] + [("split8", 30)])
+def test_plink_coding_and_k31(tgw, precision, k):
+    """PLINK coding with the largest covariate counts: K = 31 fills every
+    projection-correction slot; K = 30 leaves only the last one, which the
+    FP16 + FP8 form then takes for its FP8 pass's change of centring."""
     rng = np.random.default_rng(31)
-    n, m, k = 500, 600, 31
-    say(f"case: PLINK coding, K=31, {precision}")
+    n, m = 500, 600
+    say(f"case: PLINK coding, K={k}, {precision}")
     plink_codes = rng.choice(4, size=(m, n), p=[0.4, 0.05, 0.35, 0.2]).astype(np.uint8)
     C = rng.standard_normal((n, k))
     Y = (rng.standard_normal((n, 37)) + C[:, :3] @ rng.standard_normal((3, 37))).astype(np.float32)
@@ -235,7 +238,7 @@ def test_plink_coding_and_k31(tgw, precision):
     res, _, _ = gpu_scan(C, [Y], packed, precision, code=1)
     ref = oracle_scan(plink_codes, C, Y, plink=True)
     assert ref["df"] == n - k - 2
-    compare(res[0], ref, ref["df"], f"plink K=31 {precision} ")
+    compare(res[0], ref, ref["df"], f"plink K={k} {precision} ")
 
 
 @pytest.mark.parametrize("n,k", [(34, 31), (40, 5), (500, 10), (23_000, 10)])
