@@ -304,9 +304,9 @@ def batching_run(args, tgw, torch):
 
 def dosage_run(args, tgw, torch):
     """The workload's cohort as 8-bit dosages (one byte per sample) over
-    args.dosage_markers markers, in the FP16 split form (the 16-bit form that
-    dosages run in), reduced outputs: autotune on the dosage rows, one warm-up
-    and one timed step with the main kernel timed by HIP events."""
+    args.dosage_markers markers, in args.dosage_precision, reduced outputs:
+    autotune on the dosage rows, one warm-up and one timed step with the main
+    kernel timed by HIP events."""
     from synth import cohort_spec, dosage8_rows_torch, panel_inputs
     spec0 = cohort_spec(args.workload)
     spec = spec0.__class__(**{**spec0.__dict__, "n_markers": args.dosage_markers})
@@ -329,7 +329,7 @@ def dosage_run(args, tgw, torch):
 
     def step(profile):
         cov = tgw.fit_covariates(Cd)
-        plan = tgw.Plan([tgw.prepare_phenotypes(cov, Yd, "split16")])
+        plan = tgw.Plan([tgw.prepare_phenotypes(cov, Yd, args.dosage_precision)])
         best[0].zero_()
         hit_count.zero_()
         plan.set_hits(hits, hit_count, args.hit_threshold)
@@ -352,7 +352,8 @@ def dosage_run(args, tgw, torch):
     ms, n = plan.profile_read()
     ms /= max(1, n)
     achieved = 2.0 * N * M * P / (ms / 1e3) / 1e12
-    out = {"workload": f"{args.workload} cohort as 8-bit dosages, N={N} M={M} P={P}, FP16 hi + lo, reduced outputs",
+    form = {"split16": "FP16 hi + lo", "split8": "FP16 hi + FP8 lo", "fp32": "FP32"}[args.dosage_precision]
+    out = {"workload": f"{args.workload} cohort as 8-bit dosages, N={N} M={M} P={P}, {form}, reduced outputs",
            "value": M * P / dt, "unit": "tests/s", "ms_per_step": dt * 1e3, "main_kernel_ms": ms,
            "main_kernel_tflops": achieved, "roofline_frac": achieved / PEAK_BF16_TFLOPS}
     log(f"dosages: {dt * 1e3:.1f} ms/step, {M * P / dt:.3e} tests/s, main kernel {ms:.1f} ms, "
@@ -487,6 +488,7 @@ def main():
     ap.add_argument("--no-batching", action="store_true", help="skip the cfg5 batching-form leg")
     ap.add_argument("--dosage-markers", type=int, default=262144,
                     help="markers of the 8-bit dosage run beside the headline (0 = skip)")
+    ap.add_argument("--dosage-precision", default="split8", choices=["split16", "split8", "fp32"])
     ap.add_argument("--bed-markers", type=int, default=262144,
                     help="markers of the .bed streaming run beside the headline (0 = skip)")
     ap.add_argument("--complete-markers", type=int, default=262144,

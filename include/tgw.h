@@ -108,9 +108,11 @@ typedef enum {
  *  TGW_CODE_DOSAGE8   : one byte per sample (sample i at byte i): q = 0..254
  *                       is the expected allele count q / 127 (the imputed
  *                       dosages that the paper's BGEN input carries; Abstract,
- *                       Introduction), 255 = missing.  Runs in TGW_PREC_FP32
- *                       and TGW_PREC_SPLIT_F16 (other precisions give
- *                       TGW_ERR_UNSUPPORTED); beta and SE are per unit dosage. */
+ *                       Introduction), 255 = missing.  Runs in TGW_PREC_FP32,
+ *                       TGW_PREC_SPLIT_F16 and TGW_PREC_SPLIT_F8 (whose e4m3
+ *                       genotype operand is the FP16 value q - c rounded to
+ *                       e4m3); TGW_PREC_SPLIT gives TGW_ERR_UNSUPPORTED.  beta
+ *                       and SE are per unit dosage. */
 typedef enum { TGW_CODE_DOSAGE = 0, TGW_CODE_PLINK_BED = 1, TGW_CODE_DOSAGE8 = 2 } tgw_geno_code;
 
 typedef struct tgw_covariates tgw_covariates; /* Q of one covariate matrix   */

@@ -273,7 +273,7 @@ int gemm_grid(int idx, int prec, int mode, int n_cu, bool g8 = false);
 int tile_alias(int idx, int prec, bool g8 = false);  // smallest tile index that runs the same kernel
 hipError_t launch_gemm(int idx, int prec, int mode, const GemmArgs& a, int grid, hipStream_t s, bool g8 = false);
 // precisions that 8-bit dosages run in (exact re-centred operand: FP32 and the FP16 split)
-__host__ __device__ constexpr bool g8_supported(int prec) { return prec == kFP32 || prec == kSplit16; }
+__host__ __device__ constexpr bool g8_supported(int prec) { return prec == kFP32 || prec == kSplit16 || prec == kSplit8; }
 int wgemm_tile();  // tile shape used for the Q^T g contraction
 
 }  // namespace tgw

@@ -1542,7 +1542,7 @@ __device__ __forceinline__ void finish_block(const float* stage, const GemmArgs&
 // 2048), or FP32 q - c; a missing byte takes the marker's mu - c.
 template <int PREC, int NW, int WMF, int WN, int MODE, bool G8 = false>
 __global__ __launch_bounds__(NW * 64) void gemm_kernel(GemmArgs a) {
-  static_assert(!G8 || g8_supported(PREC), "8-bit dosages run the FP32 and FP16 split forms");
+  static_assert(!G8 || PREC == kFP32 || PREC == kSplit16, "8-bit dosages run the FP32 and FP16 split forms here");
   static_assert(MODE != kRawHL || (PREC != kFP32 && WN == 1), "the packed hi|lo operand is one split block");
   constexpr bool LO_PASS = MODE != kRawHL;
   constexpr int NT = NW * 64;
@@ -1931,20 +1931,38 @@ constexpr int waitcnt_vm_only(int vm) { return waitcnt_vm_lgkm0(vm) | (0xF << 8)
 // G8: 8-bit dosage rows (FP16 split only): each stage holds the tile's 64
 // bytes per marker; a lane reads the two dwords of its row that each K16 step
 // needs and builds FP16 q - c as the register-staged kernel does.
+// Two FP16 values (the halves of v) to OCP e4m3, round to nearest even,
+// into bytes 0 and 1 (lo) or 2 and 3 (hi) of old, the other two kept.
+// Written as the instruction itself: this compiler's builtin for it, given
+// several calls that differ only in v, emitted the conversion of the first v
+// for all of them.
+__device__ __forceinline__ uint32_t cvt_pk_e4m3_lo(uint32_t old, uint32_t v) {
+  asm("v_cvt_scalef32_pk_fp8_f16 %0, %1, 1.0" : "+v"(old) : "v"(v));
+  return old;
+}
+__device__ __forceinline__ uint32_t cvt_pk_e4m3_hi(uint32_t old, uint32_t v) {
+  asm("v_cvt_scalef32_pk_fp8_f16 %0, %1, 1.0 op_sel:[0,0,1]" : "+v"(old) : "v"(v));
+  return old;
+}
+
 template <int PREC, int MODE, int NW, int WMF, int WN = 4, bool G8 = false>
 __global__ __launch_bounds__(NW * 64) void gemm_wide_kernel(GemmArgs a) {
   static_assert(PREC != kFP32, "the wide kernel runs the split forms");
-  static_assert(!G8 || PREC == kSplit16, "8-bit dosages run the FP16 split form here");
+  static_assert(!G8 || PREC == kSplit16 || PREC == kSplit8, "8-bit dosages run the FP16 split forms here");
   static_assert((NW * WMF == 16 && WN == 4 && (WMF == 4 || WMF == 2)) ||
                     (NW == 4 && WMF == 2 && WN == 8 && PREC == kSplit8),
                 "512 x 128 tiles, or 256 x 256 for the FP8 lo form");
   constexpr bool F8 = PREC == kSplit8;
+  // 8-bit dosages in the FP16 + FP8 form: the FP8 lo operand is converted from
+  // the FP16 values of the hi pass, a step at a time, and the chunk's lo
+  // MFMAs run together at its last step
+  constexpr bool GF = F8 && G8;
   constexpr bool W2 = WMF == 2;  // FP8 lo MFMAs by column block: both fragments, WN / 4 blocks per step
   constexpr int FNS = WN / 4;    // column blocks whose FP8 lo term runs at each step (WMF = 2)
   constexpr int NT = NW * 64;
   constexpr int TM = NW * WMF * 32;
   constexpr int BB = block_bytes(PREC);
-  constexpr int NSTAGE = F8 ? (WN == 8 ? 3 : 4) : (G8 ? 2 : 3);
+  constexpr int NSTAGE = G8 ? 2 : (F8 ? (WN == 8 ? 3 : 4) : 3);
   constexpr int B_BYTES = WN * BB;  // operand chunk of the column tile
   constexpr int AB = G8 ? 64 : 16;  // bytes of a marker's chunk: 64 two-bit codes or 64 dosage bytes
   constexpr int A_BYTES = TM * AB;
@@ -2183,6 +2201,28 @@ __global__ __launch_bounds__(NW * 64) void gemm_wide_kernel(GemmArgs a) {
 #pragma unroll
       for (int fn = 0; fn < WN; ++fn) read_b8_one(st, fn, B8[fn]);
     };
+    // 8-bit dosages, FP16 + FP8 form: the FP16 values of K16 step s (as
+    // decode_g8 leaves them, dword d holds samples 16 (s >> 1) + 4 (s & 1) + d
+    // and that + 8 of this lane half) converted to e4m3 in the lo operand's
+    // layout, where dword 4 p + t holds sample 16 p + 4 k + t in byte k.  Step
+    // 2p writes bytes 0 and 1 of dword 4p + d (k = 0 and 2), step 2p + 1 bytes
+    // 2 and 3 (k = 1 and 3); one byte permutation then puts k in byte k.
+    auto cvt8 = [&](const u32x4* Av, int s, i32x8* A8v) {
+      const int p = s >> 1;
+#pragma unroll
+      for (int fm = 0; fm < WMF; ++fm)
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+          uint32_t w = (uint32_t)A8v[fm][4 * p + d];
+          if (s & 1) {
+            w = cvt_pk_e4m3_hi(w, Av[fm][d]);
+            w = __builtin_amdgcn_perm(w, w, 0x03010200u);
+          } else {
+            w = cvt_pk_e4m3_lo(w, Av[fm][d]);
+          }
+          A8v[fm][4 * p + d] = (int)w;
+        }
+    };
 
     // prologue: chunks 0..NSTAGE-1 requested, chunk 0 awaited
 #pragma unroll
@@ -2190,10 +2230,10 @@ __global__ __launch_bounds__(NW * 64) void gemm_wide_kernel(GemmArgs a) {
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     u32x4 bh[2][WN], bl[2][WN], A[2][WMF];
-    i32x8 A8[2], B8[WN];
+    i32x8 A8[GF ? WMF : 2], B8[WN];
     uint2 acur[WMF], anext[WMF];
     u32x4 araw[WMF];  // FP8 form: the next chunk's code rows, read a step early
-    constexpr bool SY = F8 && W2;  // shared selectors (spread / decode_y / decode8_y)
+    constexpr bool SY = F8 && W2 && !G8;  // shared selectors (spread / decode_y / decode8_y)
     uint32_t Y0[SY ? WMF : 1][4], Y1[SY ? WMF : 1][4];  // selectors of the first / second code dword
     uint2 dg8[WMF];  // 8-bit dosages: the two dwords of the step being decoded
     if constexpr (G8) {
@@ -2210,7 +2250,14 @@ __global__ __launch_bounds__(NW * 64) void gemm_wide_kernel(GemmArgs a) {
     } else if constexpr (!G8) {
       decode(acur, 0, A[0]);
     }
-    if constexpr (F8 && !W2) decode8(acur, 0, A8[0]);
+    if constexpr (F8 && !W2 && !G8) decode8(acur, 0, A8[0]);
+    if constexpr (GF) {
+#pragma unroll
+      for (int fm = 0; fm < WMF; ++fm)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) A8[fm][i] = 0;
+      cvt8(A[0], 0, A8);
+    }
 
     // the prologue's reads are complete before the loop; saying so keeps
     // the compiler from waiting for all LDS reads at the loop head
@@ -2222,10 +2269,26 @@ __global__ __launch_bounds__(NW * 64) void gemm_wide_kernel(GemmArgs a) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int cs = j & 1, ns = cs ^ 1;
-        if constexpr (F8 && !W2) {
+        if constexpr (F8 && !W2 && !G8) {
           if (j == 0) read_b8(st, B8);  // this chunk's lo fragments, used by all four steps
         }
-        if constexpr (F8 && W2) {
+        if constexpr (GF) {
+          if (j == 3) {
+            // the chunk's FP8 lo term, every fragment against every column
+            // block (its e4m3 operand was completed at step 2), before the
+            // barrier after which the stage is refilled
+#pragma unroll
+            for (int fn = 0; fn < WN; ++fn) {
+              i32x8 b8;
+              read_b8_one(st, fn, b8);
+#pragma unroll
+              for (int fm = 0; fm < WMF; ++fm)
+                acc[fm][fn] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A8[fm], b8, acc[fm][fn], 0, 0, 0, 127,
+                                                                              0, bscale[fn]);
+            }
+          }
+        }
+        if constexpr (F8 && W2 && !G8) {
 #pragma unroll
           for (int q = 0; q < FNS; ++q) read_b8_one(st, j * FNS + q, B8[j * FNS + q]);  // used by this step
           if (j == 0) {
@@ -2234,7 +2297,7 @@ __global__ __launch_bounds__(NW * 64) void gemm_wide_kernel(GemmArgs a) {
             for (int fm = 0; fm < WMF; ++fm) decode8_y(Y0, Y1, fm, A8[fm]);  // both fragments, whole chunk
           }
         }
-        if (F8 && j == 2) {
+        if (F8 && !G8 && j == 2) {
           // the next chunk's codes are this wave's own copies: they need
           // only its own copy of chunk ch+1 to have landed, not the barrier
           __builtin_amdgcn_s_waitcnt(waitcnt_vm_only((NSTAGE - 2) * CHUNK_OPS));
@@ -2245,6 +2308,7 @@ __global__ __launch_bounds__(NW * 64) void gemm_wide_kernel(GemmArgs a) {
           if constexpr (G8) {
             read_g8(st, j + 1, dg8);
             decode_g8(dg8, A[ns]);
+            if constexpr (GF) cvt8(A[ns], j + 1, A8);
           } else if constexpr (SY) {
             decode_y(j + 1 < 2 ? Y0 : Y1, j + 1, A[ns]);
           } else {
@@ -2257,13 +2321,13 @@ __global__ __launch_bounds__(NW * 64) void gemm_wide_kernel(GemmArgs a) {
           // wait for every copy in flight)
           __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0((NSTAGE - 2) * CHUNK_OPS));
           if constexpr (!F8 && !G8) read_a(st1, anext);  // this wave's own copies: no barrier needed
-          if constexpr (F8) pick_a(araw, anext);
+          if constexpr (F8 && !G8) pick_a(araw, anext);
           asm volatile("s_barrier" ::: "memory");
           // LDS reads before the copies: a read issued after a
           // direct-to-LDS load is held until that load completes
           read_b(st1, 0, bh[ns], bl[ns]);
           if constexpr (G8) read_g8(st1, 0, dg8);  // own copies of chunk ch + 1 have landed
-          if constexpr (!F8) dma(ch + NSTAGE, st);  // the FP8 form copies beside its lo MFMAs
+          if constexpr (!F8 || G8) dma(ch + NSTAGE, st);  // the 2-bit FP8 form copies beside its lo MFMAs
           if constexpr (G8) {
             decode_g8(dg8, A[ns]);
           } else if constexpr (SY) {
@@ -2285,7 +2349,9 @@ __global__ __launch_bounds__(NW * 64) void gemm_wide_kernel(GemmArgs a) {
         }
         // issue order: copies and LDS reads early, each behind one
         // matrix-core instruction, then the decode, a few VALU ops per MFMA
-        if (F8 && W2) {  // WMF x WN FP16 MFMA; WN hi + 2 FNS lo fragment reads (+ code rows at step 2)
+        if (GF) {
+          // 8-bit dosages, FP16 + FP8: no group hints
+        } else if (F8 && W2) {  // WMF x WN FP16 MFMA; WN hi + 2 FNS lo fragment reads (+ code rows at step 2)
           constexpr int NDS = W2 ? WN + 2 * FNS : 0;
 #pragma unroll
           for (int q = 0; q < NDS; ++q) {
@@ -2356,7 +2422,10 @@ __global__ __launch_bounds__(NW * 64) void gemm_wide_kernel(GemmArgs a) {
           }
         }
         __builtin_amdgcn_sched_barrier(0);
-        if constexpr (F8 && W2) {
+        if constexpr (GF) {
+          if (j == 3) cvt8(A[ns], 0, A8);  // the next chunk's first step (after the lo MFMAs that read A8)
+        }
+        if constexpr (F8 && W2 && !G8) {
           // FP8 lo term of column blocks j FNS .. (j + 1) FNS - 1, both fragments, whole chunk
           if (j == 3) dma(ch + NSTAGE, st);  // the stage of chunk ch is free since the barrier
 #pragma unroll
@@ -2377,7 +2446,7 @@ __global__ __launch_bounds__(NW * 64) void gemm_wide_kernel(GemmArgs a) {
           }
           __builtin_amdgcn_sched_barrier(0);
         }
-        if constexpr (F8 && !W2) {
+        if constexpr (F8 && !W2 && !G8) {
           // FP8 lo term of fragment fm = j over the whole chunk, after the
           // step's FP16 work (its operands were read at step 0); the decode
           // of the next fragment's e4m3 values rides along
@@ -2583,12 +2652,12 @@ TileShape tile_shape(int idx) { return kShapes[idx]; }
 int wgemm_tile() { return kWShape; }
 
 template <int PREC, int MODE>
-static const void* gemm_fn_g8(int idx) {  // 8-bit dosages: wide tiles 0 and 1 for the FP16 split
-  if constexpr (PREC == kSplit16) {
-    if (idx == 0) return (const void*)gemm_wide_kernel<PREC, MODE, 4, 4, 4, true>;
+static const void* gemm_fn_g8(int idx) {  // 8-bit dosages: wide tiles 0 and 1 for the FP16 splits
+  if constexpr (PREC == kSplit16 || PREC == kSplit8) {
     if (idx == 1) return (const void*)gemm_wide_kernel<PREC, MODE, 8, 2, 4, true>;
+    if (idx == 0 || PREC == kSplit8) return (const void*)gemm_wide_kernel<PREC, MODE, 4, 4, 4, true>;
   }
-  if constexpr (g8_supported(PREC)) {
+  if constexpr (PREC == kFP32 || PREC == kSplit16) {  // the register-staged shapes
     switch (idx) {
       case 3: return (const void*)gemm_kernel<PREC, 4, 2, 4, MODE, true>;
       case 4: return (const void*)gemm_kernel<PREC, 8, 1, 4, MODE, true>;
@@ -2629,6 +2698,7 @@ static const void* gemm_fn(int idx) {
 
 static TileShape effective_shape(int idx, int prec, bool g8 = false) {
   const bool wide = idx <= 1 || idx == 6;
+  if (g8 && prec == kSplit8) return kShapes[idx == 1 ? 1 : 0];
   if (g8 && prec == kSplit16 && idx <= 1) return kShapes[idx];
   if (g8) return kShapes[wide ? 2 : idx];
   if (prec == kSplit8) return kShapes[(idx == 1 || idx == 6) ? idx : 0];
@@ -2650,6 +2720,7 @@ static const void* gemm_fn_any(int idx, int prec, int mode, bool g8 = false) {
   if (g8) {
     if (prec == kSplit16) return mode == kRaw ? gemm_fn_g8<kSplit16, kRaw>(idx) : gemm_fn_g8<kSplit16, kTest>(idx);
     if (prec == kFP32) return mode == kRaw ? gemm_fn_g8<kFP32, kRaw>(idx) : gemm_fn_g8<kFP32, kTest>(idx);
+    if (prec == kSplit8) return mode == kRaw ? gemm_fn_g8<kSplit8, kRaw>(idx) : gemm_fn_g8<kSplit8, kTest>(idx);
     return nullptr;
   }
   if (prec == kSplit) return mode == kRaw ? gemm_fn<kSplit, kRaw>(idx) : gemm_fn<kSplit, kTest>(idx);

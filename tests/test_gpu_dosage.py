@@ -11,8 +11,8 @@ from tests.gpu_common import compare, gpu_scan, lib, oracle_scan, say
 
 pytestmark = pytest.mark.gpu
 
-PRECS8 = ["split16", "fp32"]
-F16_FORMS = ("split16",)
+PRECS8 = ["split16", "split8", "fp32"]
+F16_FORMS = ("split16", "split8")
 
 
 @pytest.fixture(scope="module")
@@ -95,6 +95,49 @@ def test_dosage8_contraction_missing_value(tgw, precision):
     assert np.max(np.abs(S - want) / scale) < 1e-6
 
 
+def _e4m3(x: np.ndarray) -> np.ndarray:
+    """Round to OCP FP8 E4M3 (nearest even) and back, via torch's CPU conversion."""
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(torch.float8_e4m3fn).to(
+        torch.float64).numpy()
+
+
+@pytest.mark.parametrize("tile", [0, 1])
+def test_dosage8_contraction_fp8_lo_term(tgw, tile):
+    """FP16 + FP8 form on dosages with non-integer operands: the contraction
+    equals A16 @ hi + A8 @ lo8 with A16 = q - c (a missing byte: mu - c in
+    FP16), A8 = e4m3(A16) (converted from the FP16 values), hi = fp16(2^12 v)
+    and lo8 the e4m3 lo term with the column's scale.  The lo term is about
+    2^-12 of the total, so a wrong sample order, byte placement or scale in
+    the converted FP8 operand fails the 1e-6 bound."""
+    say(f"case: dosage8 FP8 lo term, tile {tile}")
+    rng = np.random.default_rng(62 + tile)
+    n, m, p = 1000, 1100, 70
+    q = rng.integers(0, 255, size=(m, n)).astype(np.uint8)
+    q[rng.random((m, n)) < 0.03] = 255
+    V = (rng.standard_normal((n, p)) * np.exp(rng.uniform(-3, 3, size=p))[None, :] / np.sqrt(n)).astype(np.float32)
+    plan = _debug_plan(tgw, n, V, "split8", tile)
+    g = torch.from_numpy(_rows(q)).cuda()
+    S = plan.debug_contract(g, code=tgw.CODE_DOSAGE8).cpu().numpy().astype(np.float64)
+    shift, _, _ = [x.cpu().numpy() for x in plan.debug_marker_stats(g, code=tgw.CODE_DOSAGE8)]
+    obs = q < 255
+    mu = np.where(obs, q, 0).astype(np.int64).sum(1) / obs.sum(1)
+    A16 = np.where(obs, q - shift[:, None], (mu - shift)[:, None].astype(np.float16).astype(np.float64))
+    A8 = _e4m3(A16)
+    vs = V.astype(np.float64) * tgw.F16_SCALE
+    hi = vs.astype(np.float16).astype(np.float64)
+    lo = vs - hi
+    mx = np.abs(lo).max(axis=0)
+    sh = np.where(mx > 0, np.floor(np.log2(448.0 / np.where(mx > 0, mx, 1.0))), 0.0)
+    lo8 = _e4m3(lo * 2.0 ** sh[None, :]) * 2.0 ** -sh[None, :]
+    want = A16 @ hi + A8 @ lo8
+    scale = np.abs(A16) @ np.abs(vs)
+    err = np.max(np.abs(S - want) / scale)
+    lo_part = np.max(np.abs(A8 @ lo8) / scale)
+    say(f"dosage8 fp8 lo term: max rel err {err:.3g}, lo term up to {lo_part:.3g} of the scale")
+    assert lo_part > 1e-5
+    assert err < 1e-6
+
+
 @pytest.mark.parametrize("precision", PRECS8)
 def test_dosage8_cfg1_against_oracle(tgw, precision):
     spec = cohort_spec("cfg1")
@@ -143,20 +186,20 @@ def test_dosage8_unsupported_and_shape_errors(tgw):
     n = 100
     rows = _rows(np.full((4, n), 3, dtype=np.uint8))
     Y = np.random.default_rng(0).standard_normal((n, 3)).astype(np.float32)
-    for precision in ("split", "split8"):
-        with pytest.raises(tgw.TgwError) as e:
-            gpu_scan(None, [Y], rows, precision, code=tgw.CODE_DOSAGE8)
-        assert e.value.status == tgw.ERR_UNSUPPORTED
+    with pytest.raises(tgw.TgwError) as e:
+        gpu_scan(None, [Y], rows, "split", code=tgw.CODE_DOSAGE8)
+    assert e.value.status == tgw.ERR_UNSUPPORTED
     with pytest.raises(tgw.TgwError) as e:  # rows as short as 2-bit rows
         gpu_scan(None, [Y], rows[:, :32], "split16", code=tgw.CODE_DOSAGE8)
     assert e.value.status == tgw.ERR_SHAPE
 
 
-@pytest.mark.parametrize("precision,tile", [("split16", 0), ("split16", 1), ("split16", 2), ("fp32", -1)])
+@pytest.mark.parametrize("precision,tile", [("split16", 0), ("split16", 1), ("split16", 2), ("split8", 0),
+                                            ("split8", 1), ("fp32", -1)])
 def test_dosage8_full_width_against_oracle(tgw, precision, tile):
     """N = 23,000, P = 2,048: 1,536 markers (three 512-marker tiles) from the
     device generator, every output against the oracle; the FP16 split on the
-    two wide tiles and a register-staged one."""
+    two wide tiles and a register-staged one, FP16 + FP8 on both wide tiles."""
     spec = cohort_spec("cfg3")
     n = spec.n_samples
     m0, m1 = 40_000, 41_536
