@@ -175,6 +175,13 @@ def generate_genotypes(spec, torch, packed_rows_torch, row_bytes_for):
     return geno
 
 
+def resident(torch, A):
+    """A covariate or phenotype matrix as it stays in HBM: (N, cols) with the
+    samples of a column contiguous, the layout the library's fit and preparation
+    calls read, so the binding passes it through without a transposed copy."""
+    return torch.from_numpy(A).cuda().t().contiguous().t()
+
+
 def panel_scale_run(args, tgw, torch):
     """cfg4 (N=23,000, M=1,000,000, P=20,480, K=10) in the headline precision with
     reduced outputs (per-phenotype best test + hit list): one warm-up step and
@@ -185,7 +192,7 @@ def panel_scale_run(args, tgw, torch):
     t0 = time.perf_counter()
     geno = generate_genotypes(spec, torch, packed_rows_torch, row_bytes_for)
     C, Y = panel_inputs(spec, 0)
-    Cd, Yd = torch.from_numpy(C).cuda(), torch.from_numpy(Y).cuda()
+    Cd, Yd = resident(torch, C), resident(torch, Y)
     del C, Y
     P = Yd.shape[1]
     best = tgw.make_best([P])
@@ -249,8 +256,8 @@ def batching_run(args, tgw, torch):
     panels, Ps, Ks = [], [], []
     for j in range(len(spec.panels)):
         C, Y = panel_inputs(spec, j)
-        cov = tgw.fit_covariates(torch.from_numpy(C).cuda())
-        panels.append(tgw.prepare_phenotypes(cov, torch.from_numpy(Y).cuda(), args.precision))
+        cov = tgw.fit_covariates(resident(torch, C))
+        panels.append(tgw.prepare_phenotypes(cov, resident(torch, Y), args.precision))
         Ps.append(Y.shape[1])
         Ks.append(C.shape[1])
         del C, Y
@@ -320,7 +327,7 @@ def dosage_run(args, tgw, torch):
         torch.cuda.synchronize()
         log(f"dosages: {b} / {M} markers")
     C, Y = panel_inputs(spec, 0)
-    Cd, Yd = torch.from_numpy(C).cuda(), torch.from_numpy(Y).cuda()
+    Cd, Yd = resident(torch, C), resident(torch, Y)
     del C, Y
     P = Yd.shape[1]
     best = tgw.make_best([P])
@@ -429,7 +436,7 @@ def bed_stream_run(args, tgw, torch, tile):
                 del codes
         log(f"bed stream: wrote {M} x {raw_bytes} B in {time.perf_counter() - t0:.1f} s")
         C, Y = panel_inputs(spec, 0)
-        Cd, Yd = torch.from_numpy(C).cuda(), torch.from_numpy(Y).cuda()
+        Cd, Yd = resident(torch, C), resident(torch, Y)
         del C, Y
         P = Yd.shape[1]
         best = tgw.make_best([P])
@@ -495,6 +502,9 @@ def main():
                     help="markers of the run with and without missing calls beside the headline (0 = skip)")
     ap.add_argument("--bed-block", type=int, default=32768)
     ap.add_argument("--bed-threads", type=int, default=8)
+    ap.add_argument("--arena-gb", type=float, default=32.0,
+                    help="device memory of the library's handles: one torch tensor of this many GiB, handed out "
+                         "through tgw_arena (0 = hipMalloc and hipFree per handle)")
     ap.add_argument("--no-panel-scale", action="store_true",
                     help="skip the panel-scale run (cfg4: P=20,480, reduced outputs) reported beside the headline")
     args = ap.parse_args()
@@ -516,6 +526,10 @@ def main():
 
     torch.cuda.set_device(0)
     tgw.init()
+    # the handles (covariate bases, prepared panels, plans) take their memory
+    # from one torch allocation: the library's allocator calls are then host
+    # bookkeeping instead of hipMalloc / hipFree, which synchronize the device
+    arena = tgw.torch_arena(int(args.arena_gb * 2**30)).register() if args.arena_gb > 0 else None
     spec = cohort_spec(args.workload)
     if args.markers:
         spec = spec.__class__(**{**spec.__dict__, "n_markers": args.markers})
@@ -531,8 +545,8 @@ def main():
     Cds, Yds = [], []
     for j in range(n_panels):
         C, Y = panel_inputs(spec, j)
-        Cds.append(torch.from_numpy(C).cuda())
-        Yds.append(torch.from_numpy(Y).cuda())
+        Cds.append(resident(torch, C))
+        Yds.append(resident(torch, Y))
         del C, Y
     torch.cuda.synchronize()
     log(f"inputs generated in {time.perf_counter() - t0:.1f} s: N={N} M={M} panels={n_panels} P={P} K={K}")
@@ -741,6 +755,9 @@ def main():
         "dosage8_scan": dosage,
         "complete_calls": complete,
         "batching": batching,
+        "device_memory": ("hipMalloc / hipFree per handle" if arena is None else
+                          {"kind": "tgw_arena over one torch tensor", "capacity_gib": args.arena_gb,
+                           "peak_gib": arena.info().peak / 2**30}),
         "outputs": ("dense r, beta, se, t, -log10 p" if not reduced else
                     f"reduced: per-phenotype best test" + (f" + top {args.topk}" if args.topk > 0 else "")
                     + f" + hit list at -log10 p >= {args.hit_threshold} "
