@@ -1765,28 +1765,62 @@ __global__ __launch_bounds__(NW * 64) void gemm_kernel(GemmArgs a) {
         for (int fm = 0; fm < WMF; ++fm) areg[fm] = anext[fm];
       }
     } else {
-      // ring[u] holds chunk ch0 + u (ch0 a multiple of AD, so that chunk
-      // sits in LDS buffer u & 1); once used it is refilled with chunk
-      // ch0 + u + AD (the last chunk again past the end: a valid row address
-      // whose bytes are not used)
+      // ring[u] holds the rows of chunk ch0 + u and bring[v] the operand
+      // block of the chunk after it that is v mod AD (ch0 a multiple of AD,
+      // so chunk ch sits in LDS buffer ch & 1).  Each is refilled once used,
+      // with the chunk AD later (the last chunk again past the end: a valid
+      // address whose bytes are not used).  A chunk's operand block is
+      // requested AD chunks before it is copied to LDS, after that chunk's
+      // rows: waiting for it waits only for requests AD chunks old, so AD
+      // chunks of rows stay in flight (the wait counter is in order).
       ARow ring[AD][WMF];
-      load_b(0);
+      u32x4 bring[AD][WN][RPB];
+      auto load_b_to = [&](int ch, u32x4 (*dst)[RPB]) {
 #pragma unroll
-      for (int u = 0; u < AD; ++u) load_a(u < nch ? u : nch - 1, ring[u]);
-      store_b(0);
+        for (int fn = 0; fn < WN; ++fn)
+#pragma unroll
+          for (int q = 0; q < RPB; ++q)
+            dst[fn][q] = gload<u32x4>(bop[fn] + (int64_t)ch * kBlockBytes + (q * NT + tid) * 16);
+      };
+      auto store_b_from = [&](int buf, u32x4 (*src)[RPB]) {
+#pragma unroll
+        for (int fn = 0; fn < WN; ++fn)
+#pragma unroll
+          for (int q = 0; q < RPB; ++q)
+            *(u32x4*)(smem + buf * TILE_BYTES + fn * kBlockBytes + (q * NT + tid) * 16) = src[fn][q];
+      };
+      auto clamp = [&](int ch) { return ch < nch ? ch : nch - 1; };
+      load_b_to(0, bring[0]);
+      store_b_from(0, bring[0]);
+#pragma unroll
+      for (int u = 0; u < AD; ++u) {
+        load_a(clamp(u), ring[u]);
+        load_b_to(clamp(u + 1), bring[(u + 1) % AD]);
+      }
       __syncthreads();
-      for (int ch0 = 0; ch0 < nch; ch0 += AD) {
+      // whole rounds of AD chunks, with no branch inside a round (a branch
+      // per chunk left the compiler waiting for every request in flight)
+      const int nfull = nch / AD * AD;
+      for (int ch0 = 0; ch0 < nfull; ch0 += AD) {
 #pragma unroll
         for (int u = 0; u < AD; ++u) {
           const int ch = ch0 + u;
-          if (ch < nch) {
-            const bool more = ch + 1 < nch;
-            if (more) load_b(ch + 1);
-            compute(u & 1, ring[u]);
-            load_a(ch + AD < nch ? ch + AD : nch - 1, ring[u]);
-            if (more) store_b((u & 1) ^ 1);
-            __syncthreads();
-          }
+          compute(u & 1, ring[u]);
+          load_a(clamp(ch + AD), ring[u]);
+          store_b_from((u & 1) ^ 1, bring[(u + 1) % AD]);  // chunk ch + 1 (a repeat of the last past the end)
+          load_b_to(clamp(ch + 1 + AD), bring[(u + 1) % AD]);
+          __syncthreads();
+        }
+      }
+      // the last nch - nfull < AD chunks (chunk nfull + u in ring[u], its
+      // successor's operand block in bring[(u + 1) % AD])
+#pragma unroll
+      for (int u = 0; u < AD - 1; ++u) {
+        const int ch = nfull + u;
+        if (ch < nch) {
+          compute(u & 1, ring[u]);
+          if (ch + 1 < nch) store_b_from((u & 1) ^ 1, bring[(u + 1) % AD]);
+          __syncthreads();
         }
       }
     }
