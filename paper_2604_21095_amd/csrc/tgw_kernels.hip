@@ -522,9 +522,15 @@ __global__ __launch_bounds__(kPrepThreads) void prep_kernel(const void* __restri
   auto yval = [&](int c, int64_t i) -> double {
     return y_fp64 ? ((const double*)Y)[pc[c] * ldy + i] : (double)((const float*)Y)[pc[c] * ldy + i];
   };
+  // slots k >= q hold zero: every slot is loaded (past q, column q - 1
+  // again) and multiplied without a branch, which adds exact zeros only, so
+  // the loads of a sample issue together
   auto load_q = [&](int64_t i, double* qv) {
 #pragma unroll
-    for (int k = 0; k < QS; ++k) qv[k] = k < q ? Q[(int64_t)k * n_pad + i] : 0.0;
+    for (int k = 0; k < QS; ++k) {
+      const double v = Q[(int64_t)(k < q ? k : q - 1) * n_pad + i];
+      qv[k] = k < q ? v : 0.0;
+    }
   };
 
   // pass 1: means (and finiteness)
@@ -563,8 +569,7 @@ __global__ __launch_bounds__(kPrepThreads) void prep_kernel(const void* __restri
       const double yc = yval(c, i) - mean[c];
       acc[c][QS] += yc * yc;
 #pragma unroll
-      for (int k = 0; k < QS; ++k)
-        if (k < q) acc[c][k] += qv[k] * yc;
+      for (int k = 0; k < QS; ++k) acc[c][k] += qv[k] * yc;
     }
   }
   block_sum_vec<kPrepThreads, NV>(&acc[0][0], sh);
@@ -582,8 +587,7 @@ __global__ __launch_bounds__(kPrepThreads) void prep_kernel(const void* __restri
   auto yres = [&](int c, int64_t i, const double* qv) {
     double v = yval(c, i) - mean[c];
 #pragma unroll
-    for (int k = 0; k < QS; ++k)
-      if (k < q) v -= qv[k] * qty_s[c][k];
+    for (int k = 0; k < QS; ++k) v -= qv[k] * qty_s[c][k];
     return v;
   };
 
@@ -656,8 +660,7 @@ __global__ __launch_bounds__(kPrepThreads) void prep_kernel(const void* __restri
       acc[c][QS] += st;
       acc[c][QS + 1] += st * st;
 #pragma unroll
-      for (int k = 0; k < QS; ++k)
-        if (k < q) acc[c][k] += qv[k] * st;
+      for (int k = 0; k < QS; ++k) acc[c][k] += qv[k] * st;
     }
   }
   block_sum_vec<kPrepThreads, NV>(&acc[0][0], sh);
