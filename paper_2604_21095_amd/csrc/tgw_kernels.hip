@@ -793,36 +793,42 @@ __global__ __launch_bounds__(256) void stats_kernel(StatsArgs a) {
   // hold at least ceil(n / 64) such pieces
   const uint4* row = (const uint4*)(a.geno + (a.m0 + m) * a.row_bytes);
   const int64_t n16 = (a.n + 63) / 64;
-  int nmiss = 0, c1 = 0, c2 = 0;
+  // three popcounts per word: codes with the low bit set (pl), with the high
+  // bit set (ph), with both (pb); codes past n are masked to 00, which counts
+  // in none of them.  The tallies follow from these per coding below.
+  int pl = 0, ph = 0, pb = 0;
   for (int64_t d4 = lane; d4 < n16; d4 += 64) {
     const uint4 w4 = row[d4];
     const uint32_t ws[4] = {w4.x, w4.y, w4.z, w4.w};
+    const bool full = 64 * (d4 + 1) <= a.n;  // all 64 samples of this piece are real
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const uint32_t w = ws[q];
-      const int64_t nv = a.n - 16 * (4 * d4 + q);  // samples in this word
-      const uint32_t vm = nv >= 16 ? 0xffffffffu : (nv <= 0 ? 0u : ((1u << (2 * nv)) - 1u));
-      const uint32_t lo = w & 0x55555555u & vm;
-      const uint32_t hi = (w >> 1) & 0x55555555u & vm;
-      uint32_t miss, one, two;
-      if (a.code == 0) {  // dosage: 0,1,2, 3 = missing
-        miss = lo & hi;
-        one = lo & ~hi;
-        two = hi & ~lo;
-      } else {  // PLINK .bed: 0 -> 0, 1 -> missing, 2 -> 1, 3 -> 2
-        miss = lo & ~hi;
-        one = hi & ~lo;
-        two = lo & hi;
+      uint32_t w = ws[q];
+      if (!full) {
+        const int64_t nv = a.n - 16 * (4 * d4 + q);  // samples in this word
+        w &= nv >= 16 ? 0xffffffffu : (nv <= 0 ? 0u : ((1u << (2 * nv)) - 1u));
       }
-      nmiss += __popc(miss);
-      c1 += __popc(one);
-      c2 += __popc(two);
+      const uint32_t lo = w & 0x55555555u;
+      const uint32_t hi = (w >> 1) & 0x55555555u;
+      pl += __popc(lo);
+      ph += __popc(hi);
+      pb += __popc(lo & hi);
     }
   }
   for (int o = 32; o > 0; o >>= 1) {
-    nmiss += __shfl_xor(nmiss, o);
-    c1 += __shfl_xor(c1, o);
-    c2 += __shfl_xor(c2, o);
+    pl += __shfl_xor(pl, o);
+    ph += __shfl_xor(ph, o);
+    pb += __shfl_xor(pb, o);
+  }
+  int nmiss, c1, c2;
+  if (a.code == 0) {  // dosage: 0, 1, 2, 3 = missing (low bit only: 1; high bit only: 2)
+    nmiss = pb;
+    c1 = pl - pb;
+    c2 = ph - pb;
+  } else {  // PLINK .bed: 00 -> 0, 01 -> missing, 10 -> 1, 11 -> 2
+    c2 = pb;
+    nmiss = pl - pb;
+    c1 = ph - pb;
   }
   const int64_t n_obs = a.n - nmiss;
   const int64_t sg = c1 + 2 * (int64_t)c2;
