@@ -1550,7 +1550,7 @@ __device__ __forceinline__ void finish_block(const float* stage, const GemmArgs&
 // the exponent of 1024 and subtracting 1024 + c (exact for integers below
 // 2048), or FP32 q - c; a missing byte takes the marker's mu - c.
 template <int PREC, int NW, int WMF, int WN, int MODE, bool G8 = false>
-__global__ __launch_bounds__(NW * 64) void gemm_kernel(GemmArgs a) {
+__global__ __launch_bounds__(NW * 64, (WN == 1 && MODE == kRawHL) ? 4 : 1) void gemm_kernel(GemmArgs a) {
   static_assert(!G8 || PREC == kFP32 || PREC == kSplit16, "8-bit dosages run the FP32 and FP16 split forms here");
   static_assert(MODE != kRawHL || (PREC != kFP32 && WN == 1), "the packed hi|lo operand is one split block");
   constexpr bool LO_PASS = MODE != kRawHL;
