@@ -1784,19 +1784,24 @@ __global__ __launch_bounds__(NW * 64, (WN == 1 && MODE == kRawHL) ? 4 : 1) void 
       // chunks of rows stay in flight (the wait counter is in order).
       ARow ring[AD][WMF];
       u32x4 bring[AD][WN][RPB];
+      // a packed hi|lo block uses the first half of its chunk (the split
+      // layout's lo half is zero and never read): only that half is copied
+      constexpr int B_USED = MODE == kRawHL ? kBlockBytes / 2 : kBlockBytes;
       auto load_b_to = [&](int ch, u32x4 (*dst)[RPB]) {
 #pragma unroll
         for (int fn = 0; fn < WN; ++fn)
 #pragma unroll
           for (int q = 0; q < RPB; ++q)
-            dst[fn][q] = gload<u32x4>(bop[fn] + (int64_t)ch * kBlockBytes + (q * NT + tid) * 16);
+            if ((q * NT + tid) * 16 < B_USED)
+              dst[fn][q] = gload<u32x4>(bop[fn] + (int64_t)ch * kBlockBytes + (q * NT + tid) * 16);
       };
       auto store_b_from = [&](int buf, u32x4 (*src)[RPB]) {
 #pragma unroll
         for (int fn = 0; fn < WN; ++fn)
 #pragma unroll
           for (int q = 0; q < RPB; ++q)
-            *(u32x4*)(smem + buf * TILE_BYTES + fn * kBlockBytes + (q * NT + tid) * 16) = src[fn][q];
+            if ((q * NT + tid) * 16 < B_USED)
+              *(u32x4*)(smem + buf * TILE_BYTES + fn * kBlockBytes + (q * NT + tid) * 16) = src[fn][q];
       };
       auto clamp = [&](int ch) { return ch < nch ? ch : nch - 1; };
       load_b_to(0, bring[0]);
