@@ -1649,8 +1649,8 @@ __global__ __launch_bounds__(NW * 64, (WN == 1 && MODE == kRawHL) ? 4 : 1) void 
     auto dword8 = [&](const ARow& r, int k) -> uint32_t { return k < 4 ? r.q[0][k] : r.q[G8 ? 1 : 0][k & 3]; };
 
     // one chunk's decode and matrix-core steps on the staged operand tile cur
-    auto compute = [&](const int cur, const ARow* areg) __attribute__((always_inline)) {
-      const char* tile = smem + cur * TILE_BYTES;
+    auto compute = [&](const int cur, const ARow* areg, const int half) __attribute__((always_inline)) {
+      const char* tile = smem + cur * TILE_BYTES + half * (kBlockBytes / 2);
       if constexpr (PREC != kFP32) {
         u32x4 bh[WN], bl[WN];
 #pragma unroll
@@ -1767,12 +1767,77 @@ __global__ __launch_bounds__(NW * 64, (WN == 1 && MODE == kRawHL) ? 4 : 1) void 
           load_b(ch + 1);
           load_a(ch + 1, anext);
         }
-        compute(cur, areg);
+        compute(cur, areg, 0);
         if (more) store_b(cur ^ 1);
         __syncthreads();
 #pragma unroll
         for (int fm = 0; fm < WMF; ++fm) areg[fm] = anext[fm];
       }
+    } else if constexpr (MODE == kRawHL && AD == 4 && WN == 1 && RPB == 1) {
+      // A packed hi|lo block fills the first half of its 8 KiB chunk (the
+      // split layout's lo half is zero and never read), so the used halves
+      // of two chunks fill one LDS buffer: chunks 2P and 2P + 1 sit in
+      // buffer P & 1, thread t copies piece t & 255 of chunk 2P + (t >> 8),
+      // and one barrier serves two chunks.  ring[u] holds the rows of chunk
+      // ch0 + u; pring[v] holds the pair after the one in LDS whose index is
+      // v mod 2.  Rows and pairs are requested four chunks ahead (the last
+      // chunk again past the end: a valid address whose bytes are not used),
+      // and the loop runs whole rounds of four chunks without branches, so a
+      // wait covers only requests a round old (the wait counter is in order).
+      constexpr int HB = kBlockBytes / 2;
+      auto clamp = [&](int ch) { return ch < nch ? ch : nch - 1; };
+      auto load_pair = [&](int P, u32x4& dst) {
+        dst = gload<u32x4>(bop[0] + (int64_t)clamp(2 * P + (tid >> 8)) * kBlockBytes + (tid & 255) * 16);
+      };
+      auto store_pair = [&](int buf, const u32x4& src) {
+        *(u32x4*)(smem + buf * TILE_BYTES + (tid >> 8) * HB + (tid & 255) * 16) = src;
+      };
+      ARow ring[4][WMF];
+      u32x4 pring[2];
+      // requests in the order a round makes them (rows, rows, pair, rows,
+      // rows, pair), so that the counts the compiler waits for at the loop
+      // head hold for the first round as for the others
+      load_pair(0, pring[0]);
+      store_pair(0, pring[0]);
+      load_a(clamp(0), ring[0]);
+      load_a(clamp(1), ring[1]);
+      __builtin_amdgcn_sched_barrier(0);
+      load_pair(1, pring[1]);
+      __builtin_amdgcn_sched_barrier(0);
+      load_a(clamp(2), ring[2]);
+      load_a(clamp(3), ring[3]);
+      __builtin_amdgcn_sched_barrier(0);
+      load_pair(2, pring[0]);
+      __syncthreads();
+      const int nfull = nch / 4 * 4;
+      for (int ch0 = 0; ch0 < nfull; ch0 += 4) {
+        const int P = ch0 / 2;
+        compute(0, ring[0], 0);
+        load_a(clamp(ch0 + 4), ring[0]);
+        compute(0, ring[1], 1);
+        load_a(clamp(ch0 + 5), ring[1]);
+        store_pair(1, pring[1]);  // pair P + 1: chunks ch0 + 2, ch0 + 3
+        load_pair(P + 3, pring[1]);
+        __syncthreads();
+        compute(1, ring[2], 0);
+        load_a(clamp(ch0 + 6), ring[2]);
+        compute(1, ring[3], 1);
+        load_a(clamp(ch0 + 7), ring[3]);
+        store_pair(0, pring[0]);  // pair P + 2: the next round's first two chunks
+        load_pair(P + 4, pring[0]);
+        __syncthreads();
+      }
+      // the last nch - nfull < 4 chunks: the first two in buffer 0, the
+      // third's pair in pring[1]
+      const int r = nch - nfull;
+      if (r > 0) compute(0, ring[0], 0);
+      if (r > 1) compute(0, ring[1], 1);
+      if (r > 2) {
+        store_pair(1, pring[1]);
+        __syncthreads();
+        compute(1, ring[2], 0);
+      }
+      __syncthreads();  // every wave is done with the buffers before the next tile's copies
     } else {
       // ring[u] holds the rows of chunk ch0 + u and bring[v] the operand
       // block of the chunk after it that is v mod AD (ch0 a multiple of AD,
@@ -1819,7 +1884,7 @@ __global__ __launch_bounds__(NW * 64, (WN == 1 && MODE == kRawHL) ? 4 : 1) void 
 #pragma unroll
         for (int u = 0; u < AD; ++u) {
           const int ch = ch0 + u;
-          compute(u & 1, ring[u]);
+          compute(u & 1, ring[u], 0);
           load_a(clamp(ch + AD), ring[u]);
           store_b_from((u & 1) ^ 1, bring[(u + 1) % AD]);  // chunk ch + 1 (a repeat of the last past the end)
           load_b_to(clamp(ch + 1 + AD), bring[(u + 1) % AD]);
@@ -1832,7 +1897,7 @@ __global__ __launch_bounds__(NW * 64, (WN == 1 && MODE == kRawHL) ? 4 : 1) void 
       for (int u = 0; u < AD - 1; ++u) {
         const int ch = nfull + u;
         if (ch < nch) {
-          compute(u & 1, ring[u]);
+          compute(u & 1, ring[u], 0);
           if (ch + 1 < nch) store_b_from((u & 1) ^ 1, bring[(u + 1) % AD]);
           __syncthreads();
         }
