@@ -297,7 +297,8 @@ class Covariates:
 
 
 def fit_covariates(C: Optional[torch.Tensor], n_samples: Optional[int] = None, stream=None) -> Covariates:
-    """C: (N, K) float64 CUDA tensor (or None / K = 0 for intercept only)."""
+    """C: (N, K) float64 CUDA tensor (or None / K = 0 for intercept only); a
+    column-major C is passed through, any other layout is copied transposed."""
     if C is None or C.numel() == 0:
         if n_samples is None:
             n_samples = 0 if C is None else C.shape[0]
@@ -341,7 +342,9 @@ class Panel:
 
 
 def prepare_phenotypes(cov: Covariates, Y: torch.Tensor, precision="split", stream=None) -> Panel:
-    """Y: (N, P) float32/float64 CUDA tensor."""
+    """Y: (N, P) float32/float64 CUDA tensor.  The library reads a column-major
+    matrix (samples of a column contiguous, e.g. Y.t().contiguous().t()), which
+    is passed through as it is; any other layout is first copied transposed."""
     _dev_check(Y)
     prec = _PREC[precision]
     fp64 = Y.dtype == torch.float64
