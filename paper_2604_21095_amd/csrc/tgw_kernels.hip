@@ -1289,6 +1289,13 @@ template <class T>
 __device__ __forceinline__ void gstore(void* p, T v) {
   *(__attribute__((address_space(1))) T*)p = v;
 }
+// a store no kernel of the scan reads back (the dense outputs): marked
+// non-temporal, so the written lines do not displace operand and genotype
+// lines that later tiles fetch through L2
+template <class T>
+__device__ __forceinline__ void gstore_nt(void* p, T v) {
+  __builtin_nontemporal_store(v, (__attribute__((address_space(1))) T*)p);
+}
 
 // one 32x32x16 matrix-core step on 16-bit operands given as raw bits
 template <int PREC>
@@ -1439,10 +1446,10 @@ __device__ __forceinline__ void finish_block(const float* stage, const GemmArgs&
       const float t = r * sqrt_df * __builtin_amdgcn_rsqf(omr2);
       const uint32_t ob = ((uint32_t)rr * (uint32_t)od.ld + (uint32_t)r32) * 4u;
       if (okv[i]) {
-        if (odb.r) gstore(at_byte(odb.r, ob), r);
-        if (odb.beta) gstore(at_byte(odb.beta, ob), r * sp * invh);
-        if (odb.se) gstore(at_byte(odb.se, ob), sp * invh * __builtin_amdgcn_sqrtf(omr2) * inv_sqrt_df);
-        if (odb.t) gstore(at_byte(odb.t, ob), t);
+        if (odb.r) gstore_nt(at_byte(odb.r, ob), r);
+        if (odb.beta) gstore_nt(at_byte(odb.beta, ob), r * sp * invh);
+        if (odb.se) gstore_nt(at_byte(odb.se, ob), sp * invh * __builtin_amdgcn_sqrtf(omr2) * inv_sqrt_df);
+        if (odb.t) gstore_nt(at_byte(odb.t, ob), t);
       }
       rv[i] = r;
       atv[i] = fabsf(t);
@@ -1478,7 +1485,7 @@ __device__ __forceinline__ void finish_block(const float* stage, const GemmArgs&
         const bool to_tail = okv[i] && at > kTMax && at != INFINITY;
         const float nl = at <= kTMax ? nlv[i] : at;
         nlv[i] = nl;
-        if (okv[i] && !to_tail && odb.nl) gstore(at_byte(odb.nl, ((uint32_t)(h + 2 * (g + i)) * (uint32_t)od.ld + (uint32_t)r32) * 4u), nl);
+        if (okv[i] && !to_tail && odb.nl) gstore_nt(at_byte(odb.nl, ((uint32_t)(h + 2 * (g + i)) * (uint32_t)od.ld + (uint32_t)r32) * 4u), nl);
         const bool hit = okv[i] && !to_tail && at >= hit_floor && nl >= a.hits.threshold;
         rare |= (to_tail || hit) ? 1u << i : 0u;
       }
