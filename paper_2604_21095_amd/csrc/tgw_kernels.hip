@@ -2762,7 +2762,7 @@ static const TileShape kShapes[] = {
     {8, 1, 4},  // 4: 256 x 128, 8 waves
     {8, 2, 2},  // 5: 512 x 64
     {4, 2, 8},  // 6: 256 x 256, wide, one wave per SIMD (FP8 lo form; others run shape 0)
-    {8, 2, 1},  // 7: 512 x 32 (Q^T g contraction)
+    {8, 1, 1},  // 7: 256 x 32 (Q^T g contraction)
 };
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 constexpr int kWShape = 7;
@@ -2782,7 +2782,7 @@ static const void* gemm_fn_g8(int idx) {  // 8-bit dosages: wide tiles 0 and 1 f
       case 3: return (const void*)gemm_kernel<PREC, 4, 2, 4, MODE, true>;
       case 4: return (const void*)gemm_kernel<PREC, 8, 1, 4, MODE, true>;
       case 5: return (const void*)gemm_kernel<PREC, 8, 2, 2, MODE, true>;
-      case kWShape: return (const void*)gemm_kernel<PREC, 8, 2, 1, MODE, true>;
+      case kWShape: return (const void*)gemm_kernel<PREC, 8, 1, 1, MODE, true>;
       default: return (const void*)gemm_kernel<PREC, 8, 2, 4, MODE, true>;
     }
   }
@@ -2810,7 +2810,7 @@ static const void* gemm_fn(int idx) {
       case 6:  // the 256 x 256 wide shape exists for the FP8 lo form only
         if constexpr (PREC != kFP32) return (const void*)gemm_wide_kernel<PREC, MODE, 4, 4>;
         return (const void*)gemm_kernel<PREC, 8, 2, 4, MODE>;
-      case kWShape: return (const void*)gemm_kernel<PREC, 8, 2, 1, MODE>;
+      case kWShape: return (const void*)gemm_kernel<PREC, 8, 1, 1, MODE>;
     }
     return nullptr;
   }
@@ -2832,9 +2832,9 @@ static const void* gemm_fn_any(int idx, int prec, int mode, bool g8 = false) {
   if (mode == kRawHL) {  // the Q^T g shape with the packed hi|lo covariate operand
     if (idx != kWShape) return nullptr;
     if (prec == kSplit16)
-      return g8 ? (const void*)gemm_kernel<kSplit16, 8, 2, 1, kRawHL, true>
-                : (const void*)gemm_kernel<kSplit16, 8, 2, 1, kRawHL>;
-    if (prec == kSplit && !g8) return (const void*)gemm_kernel<kSplit, 8, 2, 1, kRawHL>;
+      return g8 ? (const void*)gemm_kernel<kSplit16, 8, 1, 1, kRawHL, true>
+                : (const void*)gemm_kernel<kSplit16, 8, 1, 1, kRawHL>;
+    if (prec == kSplit && !g8) return (const void*)gemm_kernel<kSplit, 8, 1, 1, kRawHL>;
     return nullptr;
   }
   if (g8) {
