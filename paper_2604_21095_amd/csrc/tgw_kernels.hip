@@ -1785,12 +1785,16 @@ __global__ __launch_bounds__(NW * 64, (WN == 1 && MODE == kRawHL) ? 4 : 1) void 
       // split layout's lo half is zero and never read), so the used halves
       // of two chunks fill one LDS buffer: chunks 2P and 2P + 1 sit in
       // buffer P & 1, thread t copies piece t & 255 of chunk 2P + (t >> 8),
-      // and one barrier serves two chunks.  ring[u] holds the rows of chunk
-      // ch0 + u; pring[v] holds the pair after the one in LDS whose index is
-      // v mod 2.  Rows and pairs are requested four chunks ahead (the last
-      // chunk again past the end: a valid address whose bytes are not used),
-      // and the loop runs whole rounds of four chunks without branches, so a
-      // wait covers only requests a round old (the wait counter is in order).
+      // and one barrier serves two chunks.  The rows go by pairs of chunks
+      // too: the lane pair of a row (h = 0, 1) reads chunks 2p and 2p + 1
+      // whole, one 16-byte piece each, and the two lanes swap halves, so a
+      // row's 128-byte line is requested in four pieces, not eight.  rraw[v]
+      // holds the pieces of the row pair ch0 + 2v, ch0 + 2v + 1; pring[v]
+      // the operand pair after the one in LDS whose index is v mod 2.  Both
+      // are requested four chunks ahead (the last chunk again past the end: a
+      // valid address whose bytes are not used), and the loop runs whole
+      // rounds of four chunks without branches, so a wait covers only
+      // requests a round old (the wait counter is in order).
       constexpr int HB = kBlockBytes / 2;
       auto clamp = [&](int ch) { return ch < nch ? ch : nch - 1; };
       auto load_pair = [&](int P, u32x4& dst) {
@@ -1799,50 +1803,74 @@ __global__ __launch_bounds__(NW * 64, (WN == 1 && MODE == kRawHL) ? 4 : 1) void 
       auto store_pair = [&](int buf, const u32x4& src) {
         *(u32x4*)(smem + buf * TILE_BYTES + (tid >> 8) * HB + (tid & 255) * 16) = src;
       };
-      ARow ring[4][WMF];
+      // ap[fm] points at this lane half's 8 bytes of chunk 0; the row starts 8 h before
+      auto load_rows = [&](int c, u32x4* dst) {  // c even: chunk c + h whole
+#pragma unroll
+        for (int fm = 0; fm < WMF; ++fm) dst[fm] = gload<u32x4>(ap[fm] - 8 * h + (int64_t)clamp(c + h) * 16);
+      };
+      // this lane half's 8 bytes of chunks c and c + 1: lane h = 0 holds chunk
+      // c and passes its second half to lane 32 + r32, which holds chunk c + 1
+      // and passes back that chunk's first half
+      auto split_rows = [&](const u32x4* src, ARow* first, ARow* second) {
+#pragma unroll
+        for (int fm = 0; fm < WMF; ++fm) {
+          const uint32_t s0 = h ? src[fm][0] : src[fm][2];
+          const uint32_t s1 = h ? src[fm][1] : src[fm][3];
+          const uint32_t r0 = (uint32_t)__shfl_xor((int)s0, 32);
+          const uint32_t r1 = (uint32_t)__shfl_xor((int)s1, 32);
+          first[fm].q[0][0] = h ? r0 : src[fm][0];
+          first[fm].q[0][1] = h ? r1 : src[fm][1];
+          second[fm].q[0][0] = h ? src[fm][2] : r0;
+          second[fm].q[0][1] = h ? src[fm][3] : r1;
+        }
+      };
+      u32x4 rraw[2][WMF];
       u32x4 pring[2];
-      // requests in the order a round makes them (rows, rows, pair, rows,
-      // rows, pair), so that the counts the compiler waits for at the loop
-      // head hold for the first round as for the others
+      ARow a0[WMF], a1[WMF];
+      // requests in the order a round makes them (rows, pair, rows, pair),
+      // so that the counts the compiler waits for at the loop head hold for
+      // the first round as for the others
       load_pair(0, pring[0]);
       store_pair(0, pring[0]);
-      load_a(clamp(0), ring[0]);
-      load_a(clamp(1), ring[1]);
+      load_rows(0, rraw[0]);
       __builtin_amdgcn_sched_barrier(0);
       load_pair(1, pring[1]);
       __builtin_amdgcn_sched_barrier(0);
-      load_a(clamp(2), ring[2]);
-      load_a(clamp(3), ring[3]);
+      load_rows(2, rraw[1]);
       __builtin_amdgcn_sched_barrier(0);
       load_pair(2, pring[0]);
       __syncthreads();
       const int nfull = nch / 4 * 4;
       for (int ch0 = 0; ch0 < nfull; ch0 += 4) {
         const int P = ch0 / 2;
-        compute(0, ring[0], 0);
-        load_a(clamp(ch0 + 4), ring[0]);
-        compute(0, ring[1], 1);
-        load_a(clamp(ch0 + 5), ring[1]);
+        split_rows(rraw[0], a0, a1);
+        compute(0, a0, 0);
+        compute(0, a1, 1);
+        load_rows(ch0 + 4, rraw[0]);
         store_pair(1, pring[1]);  // pair P + 1: chunks ch0 + 2, ch0 + 3
         load_pair(P + 3, pring[1]);
         __syncthreads();
-        compute(1, ring[2], 0);
-        load_a(clamp(ch0 + 6), ring[2]);
-        compute(1, ring[3], 1);
-        load_a(clamp(ch0 + 7), ring[3]);
+        split_rows(rraw[1], a0, a1);
+        compute(1, a0, 0);
+        compute(1, a1, 1);
+        load_rows(ch0 + 6, rraw[1]);
         store_pair(0, pring[0]);  // pair P + 2: the next round's first two chunks
         load_pair(P + 4, pring[0]);
         __syncthreads();
       }
-      // the last nch - nfull < 4 chunks: the first two in buffer 0, the
-      // third's pair in pring[1]
+      // the last nch - nfull < 4 chunks: the first two in buffer 0 and
+      // rraw[0], the third's operand pair in pring[1] and rows in rraw[1]
       const int r = nch - nfull;
-      if (r > 0) compute(0, ring[0], 0);
-      if (r > 1) compute(0, ring[1], 1);
+      if (r > 0) {
+        split_rows(rraw[0], a0, a1);
+        compute(0, a0, 0);
+        if (r > 1) compute(0, a1, 1);
+      }
       if (r > 2) {
         store_pair(1, pring[1]);
         __syncthreads();
-        compute(1, ring[2], 0);
+        split_rows(rraw[1], a0, a1);
+        compute(1, a0, 0);
       }
       __syncthreads();  // every wave is done with the buffers before the next tile's copies
     } else {
